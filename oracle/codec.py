@@ -191,6 +191,42 @@ def inverse_real(b_full: np.ndarray, c_hat: np.ndarray) -> np.ndarray:
                      optimize=True)
 
 
+def _settle_near_halves(rounded, real, q_zz, t, r, step, window=1e-6):
+    """Round-half-to-even of the EXACT dequantised reconstruction where float64
+    is too close to a half to decide.
+
+    A_rec(x, y) = sum_kl T[k, x] T[l, y] step q_kl / sqrt(n_k n_l) is a sum of
+    square roots; at pixels whose float64 value lies within `window` of a half
+    it is recomputed with 60 significant digits.  A value within 1e-40 of a
+    half is an exact half (a nonzero distance for these bounded integer
+    combinations is many orders of magnitude larger), rounded to even."""
+    from decimal import Decimal, localcontext
+    frac = np.abs(real - np.floor(real) - 0.5)
+    idx = np.argwhere(frac < window)
+    if idx.size == 0:
+        return
+    t = np.asarray(t, dtype=np.int64)
+    n = row_norms2(t)
+    zz = zigzag()[:r]
+    with localcontext() as ctx:
+        ctx.prec = 60
+        inv_sqrt = {(k, l): 1 / Decimal(int(n[k] * n[l])).sqrt() for k, l in zz}
+        half = Decimal(1) / 2
+        for b, x, y in idx:
+            acc = Decimal(0)
+            for p, (k, l) in enumerate(zz):
+                c = int(t[k, x] * t[l, y] * step * q_zz[b, p])
+                if c:
+                    acc += c * inv_sqrt[(k, l)]
+            fl = acc.to_integral_value(rounding="ROUND_FLOOR")
+            d = acc - fl - half
+            if abs(d) < Decimal("1e-40"):
+                v = fl if int(fl) % 2 == 0 else fl + 1
+            else:
+                v = fl + 1 if d > 0 else fl
+            rounded[b, x, y] = float(v)
+
+
 def clip_u8(x: np.ndarray) -> np.ndarray:
     return np.clip(x, 0, 255).astype(np.uint8)
 
@@ -243,10 +279,10 @@ def decode(coef_int: np.ndarray, t: np.ndarray, r: int, h: int, w: int,
         rounded = rne_div(num, big_l)
         real = num.astype(np.float64) / big_l
     else:
-        s = scale_diag(t)
         bq = put_zigzag(np.asarray(coef_int, dtype=np.float64) * step, r, np.float64)
         real = inverse_real(bq, approx_matrix(t))
         rounded = np.rint(real)
+        _settle_near_halves(rounded, real, np.asarray(coef_int, dtype=np.int64), t, r, step)
     return {"rec": from_blocks(clip_u8(rounded), h, w),
             "real": from_blocks(real, h, w)}
 
