@@ -1,0 +1,167 @@
+"""Benchmark: fused 8x8 approximate-DCT encode + decode + PSNR on one MI355X.
+
+Workload: a video-like stream of 300 frames 3840x2160 YUV 4:2:0 (8-bit, seeded
+AR(1) textures translated 0-4 px per frame), all frames resident in HBM.  One
+step = one launch over the whole stream: T1 forward by the fast algorithm,
+step-16 quantiser on the scaled coefficients of the first r = 10 zig-zag
+positions, int16 coefficient write-out, inverse, rounded/clipped uint8
+reconstruction write-out, per-frame per-plane squared error.
+
+Prints ONE JSON line on stdout (logs go to stderr).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_stream(spec, dev):
+    import numpy as np
+    import torch
+
+    from synth import video_base_planes
+
+    bases = [torch.from_numpy(b).to(dev) for b in video_base_planes(spec)]
+    offs = spec.offsets()
+    frames = torch.empty((spec.n_frames, spec.frame_bytes), dtype=torch.uint8, device=dev)
+    for f in range(spec.n_frames):
+        dy, dx = int(offs[f][0]), int(offs[f][1])
+        for p, ((h, w), o) in enumerate(zip(spec.plane_shapes, spec.plane_offsets)):
+            oy, ox = (dy, dx) if p == 0 else (dy // 2, dx // 2)
+            frames[f, o:o + h * w].view(h, w).copy_(bases[p][oy:oy + h, ox:ox + w])
+    torch.cuda.synchronize()
+    return frames
+
+
+def cpu_baseline(spec, n_frames: int, r: int, step: int):
+    """The CPU oracle, untuned, on the first n_frames frames (all planes)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import codec as Co
+    from oracle import matrices as M
+    from synth import video_base_planes, video_frame
+
+    bases = video_base_planes(spec)
+    samples = 0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for f in range(n_frames):
+            buf = video_frame(spec, bases, f)
+            for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets):
+                Co.evaluate(buf[o:o + h * w].reshape(h, w), M.T1, r, step)
+                samples += h * w
+        dt = time.perf_counter() - t0
+    return {"value": samples / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_frames} of the {spec.n_frames} frames, all 3 planes, "
+                      f"T1 r={r} step {step}, encode+decode+SSE, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=300)
+    ap.add_argument("--cpu-frames", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the codec shards by frame "
+              f"with no exchange beyond the per-frame SSE, which this build does not launch.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1808_02950_amd as A
+    from synth import video_spec
+
+    r, step = 10, 16
+    dev = torch.device("cuda:0")
+    A.lib()
+    spec = video_spec(n_frames=args.frames)
+    log(f"building {spec.n_frames} frames of {spec.width}x{spec.height} 4:2:0 on the GPU")
+    frames = build_stream(spec, dev)
+    planes = [(o, h, w, w) for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets)]
+    bpf = A.stream_blocks_per_frame(planes)
+    coef = torch.empty((spec.n_frames, bpf, r), dtype=torch.int16, device=dev)
+    recon = torch.empty_like(frames)
+    sse = torch.empty((spec.n_frames, 3), dtype=torch.int64, device=dev)
+
+    def step_once():
+        A.evaluate_stream(frames, planes, "T1", r, step, coef=coef, recon=recon, sse=sse)
+
+    for _ in range(args.warmup):
+        step_once()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step_once()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    samples = spec.n_frames * spec.frame_bytes
+    value = samples / (ms_per_step / 1e3) / 1e6
+
+    # algorithmic HBM bytes per launch: 64 B read + 2r B coefficients + 64 B
+    # reconstruction per 8x8 block
+    blocks = spec.n_frames * bpf
+    alg_bytes = blocks * (128 + 2 * r)
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    peak = 8000.0
+
+    s = sse.cpu().numpy()
+    npix = [h * w for h, w in spec.plane_shapes]
+    psnr_planes = [float(sum(A.psnr_from_sse(int(s[f, p]), npix[p]) for f in range(spec.n_frames))
+                         / spec.n_frames) for p in range(3)]
+    psnr_frame = float(sum(A.psnr_from_sse(int(s[f].sum()), sum(npix))
+                           for f in range(spec.n_frames)) / spec.n_frames)
+
+    out = {
+        "metric": "Mpixel/s 8x8 approx-DCT encode+decode at r=10 (% HBM peak); PSNR dB vs exact",
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"video stream {spec.n_frames} frames 3840x2160 YUV 4:2:0 uint8",
+                   "transform": "T1", "r": r, "quant_step": step,
+                   "samples_per_frame": spec.frame_bytes, "blocks_per_launch": blocks},
+        "psnr_db": {"T1_frame_mean": round(psnr_frame, 4),
+                    "T1_Y": round(psnr_planes[0], 4), "T1_U": round(psnr_planes[1], 4),
+                    "T1_V": round(psnr_planes[2], 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_frames, spec.n_frames), r, step)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/* adct.h -- C ABI of the MI355X (gfx950) library for blockwise 8x8 transform
+ * coding with low-complexity DCT approximations found by angle similarity
+ * (Oliveira, Cintra et al., "Low-complexity 8-point DCT approximation based on
+ * angle similarity for image and video coding").
+ *
+ * Conventions shared by every entry point
+ *   - Buffers are owned by the caller.  "device" pointers must point to memory
+ *     the current HIP device can access (hipMalloc or torch CUDA tensors);
+ *     "host" pointers to ordinary host memory.  The library never frees or
+ *     keeps a caller buffer past the call (device work it enqueues reads and
+ *     writes them until the stream reaches it).
+ *   - `stream` may be 0 (the null stream).  Device work is enqueued on it and
+ *     the call returns without waiting, EXCEPT where an entry point says it
+ *     synchronises (those that return host results computed on the device).
+ *   - Images are 8-bit, row-major, H rows of W pixels, `pitch` bytes between
+ *     row starts (pitch >= W).  H and W are multiples of 8.  8x8 blocks are
+ *     numbered in raster order: block b = (y/8) * (W/8) + (x/8).
+ *   - Coefficients of a block are stored in JPEG zig-zag order (row index =
+ *     vertical frequency), the first r of them, so a coefficient array is
+ *     [n_blocks][r], n_blocks = (H/8) (W/8).
+ *   - Every call returns an adct_status; on error nothing is enqueued and
+ *     adct_last_error() returns a message for the calling thread.  No C++
+ *     exception crosses this boundary.
+ */
+#ifndef ADCT_H
+#define ADCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *adct_stream_t; /* the same handle as hipStream_t */
+
+typedef enum {
+    ADCT_OK = 0,
+    ADCT_EINVAL = -1,    /* null pointer where one is required, unknown enum value,
+                            custom matrix whose rows are not orthogonal */
+    ADCT_EDIM = -2,      /* H or W <= 0 or not a multiple of 8, pitch < W, buffers
+                            not aligned as the entry point requires */
+    ADCT_ERANGE = -3,    /* r outside [1, 64], quant_step < 0, k < 1, |P| outside [1, 9] ... */
+    ADCT_EOVERFLOW = -4, /* the transform's integer stage does not fit the kernel's
+                            word size for this mode */
+    ADCT_ECAP = -5,      /* output capacity too small; counts still report the need */
+    ADCT_EDEVICE = -6,   /* a HIP runtime call failed (message has the HIP error) */
+    ADCT_ENOTSUP = -7    /* combination of arguments the library does not implement */
+} adct_status;
+
+/* Transforms.  ADCT_DCT is the exact (orthonormal) DCT, a real matrix; the
+ * others are integer matrices T whose approximation is C_hat = S T with
+ * S = diag(1/sqrt(diag(T T^T))) (Eq. (1)-(2) of the paper; S is the row
+ * normalisation, which is what Eq. (2) gives for T with orthogonal rows).
+ *   T1, T2  the matrices the paper derives (Sec. 4.1); T1 is the proposed one
+ *   LO      Lengwehasatit-Ortega, stored doubled (2 T_LO) so it is integral
+ *   T6, T4  Cintra et al. 2014;  RDCT  rounded DCT  (Sec. 2, matrix table)
+ *   CUSTOM  any int8 matrix with orthogonal rows, passed in `custom`. */
+typedef enum {
+    ADCT_DCT = 0,
+    ADCT_T1 = 1,
+    ADCT_T2 = 2,
+    ADCT_LO = 3,
+    ADCT_T6 = 4,
+    ADCT_RDCT = 5,
+    ADCT_T4 = 6,
+    ADCT_CUSTOM = 7
+} adct_transform_id;
+
+/* A low-complexity matrix: T row-major (T[k*8 + n], row k approximates DCT
+ * row k) and n[k] = (T T^T)_kk. */
+typedef struct {
+    int8_t T[64];
+    int32_t n[8];
+} adct_matrix;
+
+/* One plane (or image) inside a frame buffer: `offset` bytes from the frame
+ * start, H x W pixels, `pitch` bytes per row. */
+typedef struct {
+    int64_t offset;
+    int32_t H, W, pitch;
+    int32_t reserved;
+} adct_plane;
+
+/* ---------------------------------------------------------------- basics */
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *adct_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int adct_version(void);
+
+/* Fill *out with a built-in matrix (not ADCT_DCT / ADCT_CUSTOM).  Host only. */
+adct_status adct_matrix_get(adct_transform_id id, adct_matrix *out);
+
+/* Bound on |T A T^T| over 8-bit blocks A and on the exact inverse numerator
+ * for transform `id` (custom: `custom`), retained count r and quantiser step:
+ * *fwd_bound, *inv_bound (host, nullable).  Host only; used to pick word
+ * sizes and to report ADCT_EOVERFLOW. */
+adct_status adct_transform_bounds(adct_transform_id id, const adct_matrix *custom, int r,
+                                  int quant_step, int64_t *fwd_bound, int64_t *inv_bound);
+
+/* Host-only validation: the status the codec entry points would return for
+ * this transform, retained count r and quantiser step (want_int16: whether
+ * int16 coefficients are requested).  Quantiser steps are accepted only when
+ * the dequantised reconstruction can never sit exactly on a half (for every
+ * class n_k n_l = mu^2, step / mu must have an odd reduced denominator: a
+ * multiple of 8 for T1, T2, T6, RDCT, T4, of 32 for LO); otherwise
+ * ADCT_ENOTSUP. */
+adct_status adct_check_codec_args(adct_transform_id t, const adct_matrix *custom, int r,
+                                  int quant_step, int want_int16);
+
+/* ----------------------------------------------------------------- codec */
+
+/* Forward transform of every 8x8 block of `img` (device), keeping the first r
+ * zig-zag coefficients (Sec. 6.1.1: B = C_hat A C_hat^T, r retained).
+ *   coef_int    device int16 [n_blocks][r], nullable: the exact integer stage
+ *               Y = T A T^T (quant_step == 0) or the quantised level
+ *               q = round-half-away(B / quant_step) (quant_step > 0), where
+ *               B = s_k s_l Y.  Integer transforms only.
+ *   coef_scaled device float [n_blocks][r], nullable: B in float32.
+ * At least one output must be non-null.  For ADCT_DCT only coef_scaled (and,
+ * with quant_step > 0, coef_int holding q) are defined.
+ * ADCT_EOVERFLOW if the transform's Y does not fit int16 (LO: use coef_scaled). */
+adct_status adct_encode_blocks(const uint8_t *img, int H, int W, int pitch,
+                               adct_transform_id t, const adct_matrix *custom,
+                               int r, int quant_step,
+                               int16_t *coef_int, float *coef_scaled,
+                               adct_stream_t stream);
+
+/* Inverse of adct_encode_blocks (Sec. 6.1.1: A = C_hat^T B' C_hat, valid for
+ * T with orthogonal rows).  Input is coef_int (integer transforms; Y or q as
+ * written by encode) or coef_scaled (ADCT_DCT: B in float32); exactly one
+ * must be non-null.  Output: `out` (device) H x W uint8 with pitch_out, the
+ * reconstruction rounded half-to-even and clipped to [0, 255].  For integer
+ * transforms with quant_step == 0 the reconstruction is exact (integer
+ * arithmetic on the rational result). */
+adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled,
+                               int H, int W, uint8_t *out, int pitch_out,
+                               adct_transform_id t, const adct_matrix *custom,
+                               int r, int quant_step, adct_stream_t stream);
+
+/* Fused encode + decode + error of one image (Sec. 6.1.1, MSE and PSNR).
+ *   coef_int   device int16 [n_blocks][r], nullable (as in encode)
+ *   recon      device uint8, pitch_out, nullable
+ *   sse_dev    device uint64[1], required: set to sum (rec - img)^2
+ *   mse_host, psnr_host  host doubles, nullable; if either is non-null the
+ *              call synchronises `stream` and fills them (PSNR = +inf when
+ *              the error is 0; PSNR = 10 log10(255^2 / MSE)). */
+adct_status adct_evaluate_coding(const uint8_t *img, int H, int W, int pitch,
+                                 adct_transform_id t, const adct_matrix *custom,
+                                 int r, int quant_step,
+                                 int16_t *coef_int, uint8_t *recon, int pitch_out,
+                                 uint64_t *sse_dev, double *mse_host, double *psnr_host,
+                                 adct_stream_t stream);
+
+/* Fused encode + decode + error over a stream of frames in ONE launch.
+ * Frame f starts at frames + f * frame_stride (device); plane p of it is
+ * planes[p] (host array, n_planes <= 4).  Coefficients go to
+ * coef + ((f * blocks_per_frame) + plane_block_offset[p] + b) * r, where
+ * planes' blocks are numbered consecutively in plane order; recon uses the
+ * same offsets and pitches as the input, at recon + f * frame_stride_out.
+ * sse (device uint64 [n_frames][n_planes]) is zeroed by the call, then
+ * accumulated.  coef and recon are nullable. */
+adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                 const adct_plane *planes, int n_planes,
+                                 adct_transform_id t, const adct_matrix *custom,
+                                 int r, int quant_step,
+                                 int16_t *coef, uint8_t *recon, int64_t frame_stride_out,
+                                 uint64_t *sse, adct_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADCT_H */

@@ -1,0 +1,232 @@
+"""Python binding of libadct.so, the MI355X library for blockwise 8x8 transform
+coding with angle-similarity DCT approximations.
+
+Argument marshalling only: every step of the coding path runs in the library's
+HIP kernels.  torch is used for device memory and streams.  The library must
+have been built (`paper_1808_02950_amd._build.build()`); importing the binding
+on a machine without it raises immediately -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libadct.so")
+
+# transform ids (adct_transform_id)
+DCT, T1, T2, LO, T6, RDCT, T4, CUSTOM = range(8)
+TRANSFORM_IDS = {"DCT": DCT, "T1": T1, "T2": T2, "LO": LO, "T6": T6,
+                 "RDCT": RDCT, "T4": T4, "CUSTOM": CUSTOM}
+
+STATUS = {0: "ADCT_OK", -1: "ADCT_EINVAL", -2: "ADCT_EDIM", -3: "ADCT_ERANGE",
+          -4: "ADCT_EOVERFLOW", -5: "ADCT_ECAP", -6: "ADCT_EDEVICE", -7: "ADCT_ENOTSUP"}
+
+
+class AdctError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int8 * 64), ("n", ctypes.c_int32 * 8)]
+
+
+class Plane(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+_SIGNATURES = {
+    "adct_last_error": (ctypes.c_char_p, []),
+    "adct_version": (_I, []),
+    "adct_matrix_get": (_I, [_I, ctypes.POINTER(Matrix)]),
+    "adct_check_codec_args": (_I, [_I, ctypes.POINTER(Matrix), _I, _I, _I]),
+    "adct_transform_bounds": (_I, [_I, ctypes.POINTER(Matrix), _I, _I,
+                                   ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "adct_encode_blocks": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(Matrix), _I, _I, _P, _P, _P]),
+    "adct_decode_blocks": (_I, [_P, _P, _I, _I, _P, _I, _I, ctypes.POINTER(Matrix), _I, _I, _P]),
+    "adct_evaluate_coding": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(Matrix), _I, _I, _P, _P, _I,
+                                  _P, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), _P]),
+    "adct_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I,
+                                  ctypes.POINTER(Matrix), _I, _I, _P, _P, _I64, _P, _P]),
+}
+
+
+def lib():
+    """Load libadct.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1808_02950_amd._build.build()")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise AdctError(status, lib().adct_last_error().decode())
+
+
+def _tid(t) -> int:
+    return TRANSFORM_IDS[t] if isinstance(t, str) else int(t)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need_cuda(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+
+
+# ---------------------------------------------------------------- host-only
+
+def version() -> int:
+    return lib().adct_version()
+
+
+def matrix_get(t) -> np.ndarray:
+    m = Matrix()
+    _check(lib().adct_matrix_get(_tid(t), ctypes.byref(m)))
+    return np.array(list(m.T), dtype=np.int64).reshape(8, 8)
+
+
+def transform_bounds(t, r: int, quant_step: int = 0, custom: np.ndarray | None = None):
+    m = _matrix_struct(custom) if custom is not None else None
+    f, i = _I64(), _I64()
+    _check(lib().adct_transform_bounds(_tid(t), ctypes.byref(m) if m else None, r, quant_step,
+                                       ctypes.byref(f), ctypes.byref(i)))
+    return f.value, i.value
+
+
+def _matrix_struct(t: np.ndarray) -> Matrix:
+    t = np.asarray(t, dtype=np.int64).reshape(8, 8)
+    m = Matrix()
+    for k in range(64):
+        m.T[k] = int(t.ravel()[k])
+    for k in range(8):
+        m.n[k] = int(np.dot(t[k], t[k]))
+    return m
+
+
+# ---------------------------------------------------------------- codec
+
+def n_blocks(h: int, w: int) -> int:
+    return (h // 8) * (w // 8)
+
+
+def encode_blocks(img, t, r: int, quant_step: int = 0, want_int: bool = True,
+                  want_scaled: bool = False, coef_int=None, coef_scaled=None, stream=None):
+    """adct_encode_blocks.  img: uint8 CUDA tensor (H, W) (row pitch = stride(0)).
+    Returns (coef_int or None, coef_scaled or None), each (n_blocks, r)."""
+    import torch
+    _need_cuda(img, torch.uint8, "img")
+    h, w = img.shape
+    nb = n_blocks(h, w)
+    if want_int and coef_int is None:
+        coef_int = torch.empty((nb, r), dtype=torch.int16, device=img.device)
+    if want_scaled and coef_scaled is None:
+        coef_scaled = torch.empty((nb, r), dtype=torch.float32, device=img.device)
+    _check(lib().adct_encode_blocks(_ptr(img), h, w, img.stride(0), _tid(t), None, r, quant_step,
+                                    _ptr(coef_int), _ptr(coef_scaled), _stream(stream)))
+    return coef_int, coef_scaled
+
+
+def decode_blocks(coef_int, h: int, w: int, t, r: int, quant_step: int = 0, out=None,
+                  coef_scaled=None, stream=None):
+    """adct_decode_blocks.  Returns the (H, W) uint8 reconstruction."""
+    import torch
+    dev = (coef_int if coef_int is not None else coef_scaled).device
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    _check(lib().adct_decode_blocks(_ptr(coef_int), _ptr(coef_scaled), h, w, _ptr(out),
+                                    out.stride(0), _tid(t), None, r, quant_step, _stream(stream)))
+    return out
+
+
+@dataclass
+class Evaluation:
+    sse: int
+    mse: float
+    psnr: float
+
+
+def evaluate_coding(img, t, r: int, quant_step: int = 0, coef_int=None, recon=None,
+                    sse=None, stream=None) -> Evaluation:
+    """adct_evaluate_coding (synchronises the stream to return MSE / PSNR)."""
+    import torch
+    _need_cuda(img, torch.uint8, "img")
+    h, w = img.shape
+    if sse is None:
+        sse = torch.empty(1, dtype=torch.int64, device=img.device)
+    mse, psnr = ctypes.c_double(), ctypes.c_double()
+    _check(lib().adct_evaluate_coding(_ptr(img), h, w, img.stride(0), _tid(t), None, r, quant_step,
+                                      _ptr(coef_int), _ptr(recon),
+                                      recon.stride(0) if recon is not None else 0,
+                                      _ptr(sse), ctypes.byref(mse), ctypes.byref(psnr),
+                                      _stream(stream)))
+    return Evaluation(int(sse.item()), mse.value, psnr.value)
+
+
+def planes_struct(planes) -> ctypes.Array:
+    arr = (Plane * len(planes))()
+    for i, (off, h, w, pitch) in enumerate(planes):
+        arr[i].offset, arr[i].H, arr[i].W, arr[i].pitch = int(off), int(h), int(w), int(pitch)
+    return arr
+
+
+def evaluate_stream(frames, planes, t, r: int, quant_step: int = 0, coef=None, recon=None,
+                    sse=None, stream=None):
+    """adct_evaluate_stream over frames (uint8 CUDA tensor (n_frames, frame_bytes)).
+    planes: list of (offset, H, W, pitch).  Returns the device SSE tensor
+    (n_frames, n_planes) int64 (uint64 values); does not synchronise."""
+    import torch
+    _need_cuda(frames, torch.uint8, "frames")
+    nf = frames.shape[0]
+    if sse is None:
+        sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
+    arr = planes_struct(planes)
+    _check(lib().adct_evaluate_stream(_ptr(frames), frames.stride(0), nf, arr, len(planes), _tid(t),
+                                      None, r, quant_step, _ptr(coef), _ptr(recon),
+                                      recon.stride(0) if recon is not None else 0,
+                                      _ptr(sse), _stream(stream)))
+    return sse
+
+
+def stream_blocks_per_frame(planes) -> int:
+    return sum(n_blocks(h, w) for _, h, w, _ in planes)
+
+
+def psnr_from_sse(sse: int, npix: int) -> float:
+    if sse == 0:
+        return math.inf
+    return 10.0 * math.log10(255.0 * 255.0 * npix / sse)

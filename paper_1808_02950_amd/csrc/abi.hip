@@ -1,0 +1,387 @@
+// C ABI entry points: argument validation, constant set-up and dispatch.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "adct_internal.hpp"
+
+namespace adct {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+adct_status fail(adct_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+adct_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return ADCT_EDEVICE;
+}
+
+namespace {
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Small fill kernel instead of hipMemsetAsync so the call stays graph-safe.
+adct_status zero_u64(uint64_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return ADCT_OK;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u64, dim3(unsigned(blocks)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long *>(p), n, 0ull);
+    ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
+}
+
+bool is_builtin_int(int t) { return t >= ADCT_T1 && t <= ADCT_T4; }
+
+void matrix_of(int t, adct_matrix *m) {
+    const Mat8 &src = builtin(t);
+    for (int k = 0; k < 8; ++k) {
+        int32_t s = 0;
+        for (int c = 0; c < 8; ++c) {
+            m->T[8 * k + c] = src.m[k][c];
+            s += int32_t(src.m[k][c]) * src.m[k][c];
+        }
+        m->n[k] = s;
+    }
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Exact bound of |Y_kl| over 8-bit blocks, max over (k, l).
+int64_t fwd_bound(const adct_matrix &m) {
+    int64_t best = 0;
+    for (int k = 0; k < 8; ++k)
+        for (int l = 0; l < 8; ++l) {
+            int64_t pos = 0, neg = 0;
+            for (int u = 0; u < 8; ++u)
+                for (int v = 0; v < 8; ++v) {
+                    const int64_t c = int64_t(m.T[8 * k + u]) * m.T[8 * l + v];
+                    if (c > 0) pos += c; else neg -= c;
+                }
+            best = std::max(best, 255 * std::max(pos, neg));
+        }
+    return best;
+}
+
+int64_t lcm64(int64_t a, int64_t b) {
+    int64_t x = a, y = b;
+    while (y) { const int64_t t = x % y; x = y; y = t; }
+    return a / x * b;
+}
+
+// Exact bound of the inverse numerator T^T (Y' o c c^T) T over 8-bit blocks for
+// the zig-zag prefix of length r.
+int64_t inv_bound(const adct_matrix &m, int r) {
+    int64_t l1 = 1;
+    for (int k = 0; k < 8; ++k) l1 = lcm64(l1, m.n[k]);
+    int64_t c[8];
+    for (int k = 0; k < 8; ++k) c[k] = l1 / m.n[k];
+    int64_t best = 0;
+    for (int x = 0; x < 8; ++x)
+        for (int y = 0; y < 8; ++y) {
+            int64_t kern[64] = {0};
+            for (int z = 0; z < r; ++z) {
+                const int k = kZZ[z] >> 3, l = kZZ[z] & 7;
+                const int64_t w = c[k] * c[l] * m.T[8 * k + x] * m.T[8 * l + y];
+                if (!w) continue;
+                for (int u = 0; u < 8; ++u)
+                    for (int v = 0; v < 8; ++v) kern[8 * u + v] += w * m.T[8 * k + u] * m.T[8 * l + v];
+            }
+            int64_t pos = 0, neg = 0;
+            for (int i = 0; i < 64; ++i) {
+                if (kern[i] > 0) pos += kern[i]; else neg -= kern[i];
+            }
+            best = std::max(best, 255 * std::max(pos, neg));
+        }
+    return best;
+}
+
+struct Prepared {
+    adct_matrix m;
+    int band;
+    bool quant;
+};
+
+adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int quant_step,
+                    bool need_int16_coef, Prepared *out, CodecArgs *a) {
+    if (t == ADCT_DCT) return fail(ADCT_ENOTSUP, "the exact DCT runs through the MFMA comparator path");
+    if (t == ADCT_CUSTOM) return fail(ADCT_ENOTSUP, "custom matrices are not supported by the fused codec");
+    if (!is_builtin_int(t)) return fail(ADCT_EINVAL, "unknown transform id");
+    if (r < 1 || r > 64) return fail(ADCT_ERANGE, "r must be in [1, 64]");
+    if (quant_step < 0 || quant_step > 65535) return fail(ADCT_ERANGE, "quant_step must be in [0, 65535]");
+    (void)custom;
+    matrix_of(t, &out->m);
+    out->band = r <= 10 ? 3 : 14;
+    out->quant = quant_step > 0;
+    const int64_t fb = fwd_bound(out->m);
+    if (!out->quant) {
+        if (need_int16_coef && fb > 32767)
+            return fail(ADCT_EOVERFLOW, "the integer stage of this transform exceeds int16; request coef_scaled");
+        if (2 * inv_bound(out->m, r) + (int64_t(1) << 22) >= (int64_t(1) << 31))
+            return fail(ADCT_EOVERFLOW, "inverse numerator exceeds int32");
+    }
+    const int32_t *n = out->m.n;
+    if (out->quant) {
+        // The dequantised reconstruction sum_kl T T step q / sqrt(n_k n_l) can sit
+        // exactly on a half only through its rational part; that part has an odd
+        // denominator (so never a half) when every perfect-square class mu^2 =
+        // n_k n_l gives step / mu an odd reduced denominator.  Steps without
+        // this property are refused: float64 could not decide those halves.
+        for (int k = 0; k < 8; ++k)
+            for (int l = 0; l < 8; ++l) {
+                const int64_t prod = int64_t(n[k]) * n[l];
+                const int64_t mu = int64_t(llround(sqrt(double(prod))));
+                if (mu * mu != prod) continue;
+                int64_t g = mu, b = quant_step;
+                while (b) { const int64_t t2 = g % b; g = b; b = t2; }
+                if (((mu / g) & 1) == 0)
+                    return fail(ADCT_ENOTSUP, "quant_step admits exact half ties in the reconstruction "
+                                              "of this transform (step / sqrt(n_k n_l) must have an odd "
+                                              "reduced denominator for every rational class)");
+            }
+    }
+    for (int k = 0; k < 8; ++k)
+        for (int l = 0; l < 8; ++l) {
+            const int i = 8 * k + l;
+            const int64_t prod = int64_t(n[k]) * n[l];
+            const double sks = 1.0 / sqrt(double(prod));
+            a->bscale[i] = float(sks);
+            a->dq[i] = double(quant_step) * sks;
+            a->qden[i] = 0;
+            a->qinv[i] = 0.f;
+            a->qalpha[i] = 0.0;
+            if (out->quant) {
+                const int64_t mu = int64_t(llround(sqrt(double(prod))));
+                if (mu * mu == prod) {
+                    const int64_t d2 = 2 * int64_t(quant_step) * mu;
+                    if (2 * fb + d2 >= (int64_t(1) << 24) || d2 >= (int64_t(1) << 23))
+                        return fail(ADCT_ERANGE, "quant_step too large for the exact integer quantiser");
+                    a->qden[i] = int32_t(d2);
+                    a->qinv[i] = float(1.0 / double(d2));
+                } else {
+                    a->qalpha[i] = sks / double(quant_step);
+                }
+            }
+        }
+    return ADCT_OK;
+}
+
+adct_status check_plane(const void *base, int64_t offset, int H, int W, int pitch, const char *what) {
+    if (H <= 0 || W <= 0 || (H & 7) || (W & 7))
+        return fail(ADCT_EDIM, std::string(what) + ": H and W must be positive multiples of 8");
+    if (pitch < W) return fail(ADCT_EDIM, std::string(what) + ": pitch < W");
+    if ((pitch & 7) || (offset & 7) || !aligned(base, 8))
+        return fail(ADCT_EDIM, std::string(what) + ": base, offsets and pitch must be 8-byte aligned");
+    if (int64_t(H / 8) * (W / 8) > (int64_t(1) << 30))
+        return fail(ADCT_EDIM, std::string(what) + ": too many blocks");
+    return ADCT_OK;
+}
+
+// Set up plane descriptors; returns waves per frame.
+int setup_planes(CodecArgs *a, const adct_plane *pl, int np) {
+    int waves = 0, blocks = 0;
+    for (int p = 0; p < np; ++p) {
+        PlaneArg &d = a->pl[p];
+        d.in_off = pl[p].offset;
+        d.out_off = pl[p].offset;
+        d.pitch_in = pl[p].pitch;
+        d.pitch_out = pl[p].pitch;
+        d.nbx = pl[p].W / 8;
+        d.nblocks = (pl[p].H / 8) * (pl[p].W / 8);
+        d.wave_start = waves;
+        d.block_off = blocks;
+        waves += (d.nblocks + 63) / 64;
+        blocks += d.nblocks;
+    }
+    a->n_planes = np;
+    a->blocks_per_frame = blocks;
+    a->waves_per_frame = waves;
+    return waves;
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+static adct_status stream_impl(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                               const adct_plane *planes, int n_planes,
+                               adct_transform_id t, const adct_matrix *custom,
+                               int r, int quant_step, int16_t *coef, uint8_t *recon,
+                               int64_t frame_stride_out, int pitch_out_override,
+                               uint64_t *sse, adct_stream_t stream) {
+    if (!frames || !planes || !sse) return fail(ADCT_EINVAL, "frames, planes and sse are required");
+    if (n_frames < 1) return fail(ADCT_ERANGE, "n_frames must be >= 1");
+    if (n_planes < 1 || n_planes > kMaxPlanes) return fail(ADCT_ERANGE, "n_planes must be in [1, 4]");
+    if (frame_stride < 0 || (frame_stride & 7)) return fail(ADCT_EDIM, "frame_stride must be a non-negative multiple of 8");
+    if (recon && (frame_stride_out < 0 || (frame_stride_out & 7) || !aligned(recon, 8)))
+        return fail(ADCT_EDIM, "recon must be 8-byte aligned with a frame stride multiple of 8");
+    if (coef && !aligned(coef, 4)) return fail(ADCT_EDIM, "coef must be 4-byte aligned");
+    if (!aligned(sse, 8)) return fail(ADCT_EDIM, "sse must be 8-byte aligned");
+    for (int p = 0; p < n_planes; ++p) {
+        adct_status st = check_plane(frames, planes[p].offset, planes[p].H, planes[p].W, planes[p].pitch, "plane");
+        if (st) return st;
+    }
+    CodecArgs a;
+    memset(&a, 0, sizeof(a));
+    Prepared pr;
+    adct_status st = prepare(t, custom, r, quant_step, coef != nullptr, &pr, &a);
+    if (st) return st;
+    const int wpf = setup_planes(&a, planes, n_planes);
+    if (pitch_out_override > 0)
+        for (int p = 0; p < n_planes; ++p) a.pl[p].pitch_out = pitch_out_override;
+    if (int64_t(wpf) * n_frames >= (int64_t(1) << 31) / 4)
+        return fail(ADCT_EDIM, "stream too large for one launch");
+    if (int64_t(a.blocks_per_frame) * n_frames * r >= (int64_t(1) << 62))
+        return fail(ADCT_EDIM, "coefficient buffer too large");
+    a.in = frames;
+    a.out = recon;
+    a.coef = coef;
+    a.sse = reinterpret_cast<unsigned long long *>(sse);
+    a.fs_in = frame_stride;
+    a.fs_out = frame_stride_out;
+    a.n_frames = n_frames;
+    a.r = r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    st = zero_u64(sse, int64_t(n_frames) * n_planes, s);
+    if (st) return st;
+    return launch_codec(t, pr.band, pr.quant, kEvaluate, a, wpf * n_frames, s);
+}
+
+extern "C" {
+
+const char *adct_last_error(void) { return g_err.c_str(); }
+
+int adct_version(void) { return 100; }
+
+adct_status adct_matrix_get(adct_transform_id id, adct_matrix *out) {
+    if (!out) return fail(ADCT_EINVAL, "out is null");
+    if (!is_builtin_int(id)) return fail(ADCT_EINVAL, "not a built-in integer transform");
+    matrix_of(id, out);
+    return ADCT_OK;
+}
+
+adct_status adct_check_codec_args(adct_transform_id t, const adct_matrix *custom, int r,
+                                  int quant_step, int want_int16) {
+    CodecArgs a;
+    Prepared pr;
+    return prepare(t, custom, r, quant_step, want_int16 != 0, &pr, &a);
+}
+
+adct_status adct_transform_bounds(adct_transform_id id, const adct_matrix *custom, int r,
+                                  int quant_step, int64_t *fwd, int64_t *inv) {
+    adct_matrix m;
+    if (id == ADCT_CUSTOM) {
+        if (!custom) return fail(ADCT_EINVAL, "custom matrix is null");
+        m = *custom;
+    } else if (is_builtin_int(id)) {
+        matrix_of(id, &m);
+    } else {
+        return fail(ADCT_EINVAL, "not an integer transform");
+    }
+    if (r < 1 || r > 64) return fail(ADCT_ERANGE, "r must be in [1, 64]");
+    if (quant_step < 0) return fail(ADCT_ERANGE, "quant_step < 0");
+    for (int k = 0; k < 8; ++k)
+        if (m.n[k] <= 0) return fail(ADCT_EINVAL, "matrix has a zero row");
+    if (fwd) *fwd = fwd_bound(m);
+    if (inv) *inv = inv_bound(m, r);
+    return ADCT_OK;
+}
+
+adct_status adct_encode_blocks(const uint8_t *img, int H, int W, int pitch,
+                               adct_transform_id t, const adct_matrix *custom,
+                               int r, int quant_step, int16_t *coef_int, float *coef_scaled,
+                               adct_stream_t stream) {
+    if (!img) return fail(ADCT_EINVAL, "img is null");
+    if (!coef_int && !coef_scaled) return fail(ADCT_EINVAL, "no output requested");
+    adct_status st = check_plane(img, 0, H, W, pitch, "img");
+    if (st) return st;
+    if ((coef_int && !aligned(coef_int, 4)) || (coef_scaled && !aligned(coef_scaled, 4)))
+        return fail(ADCT_EDIM, "coefficient buffers must be 4-byte aligned");
+    CodecArgs a;
+    memset(&a, 0, sizeof(a));
+    Prepared pr;
+    st = prepare(t, custom, r, quant_step, coef_int != nullptr, &pr, &a);
+    if (st) return st;
+    adct_plane pl = {0, H, W, pitch, 0};
+    const int waves = setup_planes(&a, &pl, 1);
+    a.in = img;
+    a.coef = coef_int;
+    a.coef_f = coef_scaled;
+    a.n_frames = 1;
+    a.r = r;
+    return launch_codec(t, pr.band, pr.quant, kEncode, a, waves, reinterpret_cast<hipStream_t>(stream));
+}
+
+adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled,
+                               int H, int W, uint8_t *out, int pitch_out,
+                               adct_transform_id t, const adct_matrix *custom,
+                               int r, int quant_step, adct_stream_t stream) {
+    if (!out) return fail(ADCT_EINVAL, "out is null");
+    if ((coef_int != nullptr) == (coef_scaled != nullptr))
+        return fail(ADCT_EINVAL, "exactly one of coef_int / coef_scaled must be given");
+    if (coef_scaled) return fail(ADCT_ENOTSUP, "float coefficients decode through the exact-DCT path");
+    adct_status st = check_plane(out, 0, H, W, pitch_out, "out");
+    if (st) return st;
+    if (!aligned(coef_int, 4)) return fail(ADCT_EDIM, "coef_int must be 4-byte aligned");
+    CodecArgs a;
+    memset(&a, 0, sizeof(a));
+    Prepared pr;
+    st = prepare(t, custom, r, quant_step, true, &pr, &a);
+    if (st) return st;
+    adct_plane pl = {0, H, W, pitch_out, 0};
+    const int waves = setup_planes(&a, &pl, 1);
+    a.out = out;
+    a.coef = const_cast<int16_t *>(coef_int);
+    a.n_frames = 1;
+    a.r = r;
+    return launch_codec(t, pr.band, pr.quant, kDecode, a, waves, reinterpret_cast<hipStream_t>(stream));
+}
+
+adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                 const adct_plane *planes, int n_planes,
+                                 adct_transform_id t, const adct_matrix *custom,
+                                 int r, int quant_step, int16_t *coef, uint8_t *recon,
+                                 int64_t frame_stride_out, uint64_t *sse, adct_stream_t stream) {
+    return stream_impl(frames, frame_stride, n_frames, planes, n_planes, t, custom, r, quant_step,
+                       coef, recon, frame_stride_out, 0, sse, stream);
+}
+
+adct_status adct_evaluate_coding(const uint8_t *img, int H, int W, int pitch,
+                                 adct_transform_id t, const adct_matrix *custom,
+                                 int r, int quant_step, int16_t *coef_int, uint8_t *recon,
+                                 int pitch_out, uint64_t *sse_dev, double *mse_host,
+                                 double *psnr_host, adct_stream_t stream) {
+    if (!img || !sse_dev) return fail(ADCT_EINVAL, "img and sse_dev are required");
+    adct_status st = check_plane(img, 0, H, W, pitch, "img");
+    if (st) return st;
+    if (recon) {
+        st = check_plane(recon, 0, H, W, pitch_out, "recon");
+        if (st) return st;
+    }
+    adct_plane pl = {0, H, W, pitch, 0};
+    st = stream_impl(img, 0, 1, &pl, 1, t, custom, r, quant_step, coef_int, recon, 0,
+                     recon ? pitch_out : 0, sse_dev, stream);
+    if (st) return st;
+    if (mse_host || psnr_host) {
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        uint64_t h = 0;
+        ADCT_HIP(hipMemcpyAsync(&h, sse_dev, sizeof(h), hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipStreamSynchronize(s));
+        const double mse = double(h) / (double(H) * double(W));
+        if (mse_host) *mse_host = mse;
+        if (psnr_host) *psnr_host = (h == 0) ? INFINITY : 10.0 * log10(255.0 * 255.0 / mse);
+    }
+    return ADCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Internal definitions shared by the library's translation units (not the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <numeric>
+#include <string>
+
+#include "adct.h"
+
+namespace adct {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+adct_status fail(adct_status s, const std::string &msg);
+adct_status hip_fail(hipError_t e, const char *what);
+
+#define ADCT_HIP(call)                                                 \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ::adct::hip_fail(e_, #call);      \
+    } while (0)
+
+// ---------------------------------------------------------------- matrices
+//
+// The library's own copy of the integer matrices (T LO stored doubled so it is
+// integral; the scale S is invariant to a positive factor).  T1 and T2 are the
+// matrices the paper derives (Sec. 4.1); RDCT, LO, T6, T4 are from its table of
+// common low-complexity matrices (Sec. 2).
+
+struct Mat8 {
+    int8_t m[8][8];
+};
+
+constexpr Mat8 kT1 = {{{1, 1, 1, 1, 1, 1, 1, 1},
+                       {2, 2, 1, 0, 0, -1, -2, -2},
+                       {2, 1, -1, -2, -2, -1, 1, 2},
+                       {1, 0, -2, -2, 2, 2, 0, -1},
+                       {1, -1, -1, 1, 1, -1, -1, 1},
+                       {2, -2, 0, 1, -1, 0, 2, -2},
+                       {1, -2, 2, -1, -1, 2, -2, 1},
+                       {0, -1, 2, -2, 2, -2, 1, 0}}};
+
+constexpr Mat8 kT2 = {{{1, 1, 1, 1, 1, 1, 1, 1},
+                       {2, 1, 2, 0, 0, -2, -1, -2},
+                       {2, 1, -1, -2, -2, -1, 1, 2},
+                       {2, 0, -2, -1, 1, 2, 0, -2},
+                       {1, -1, -1, 1, 1, -1, -1, 1},
+                       {1, -2, 0, 2, -2, 0, 2, -1},
+                       {1, -2, 2, -1, -1, 2, -2, 1},
+                       {0, -2, 1, -2, 2, -1, 2, 0}}};
+
+constexpr Mat8 kLOx2 = {{{2, 2, 2, 2, 2, 2, 2, 2},
+                         {2, 2, 2, 0, 0, -2, -2, -2},
+                         {2, 1, -1, -2, -2, -1, 1, 2},
+                         {2, 0, -2, -2, 2, 2, 0, -2},
+                         {2, -2, -2, 2, 2, -2, -2, 2},
+                         {2, -2, 0, 2, -2, 0, 2, -2},
+                         {1, -2, 2, -1, -1, 2, -2, 1},
+                         {0, -2, 2, -2, 2, -2, 2, 0}}};
+
+constexpr Mat8 kT6 = {{{1, 1, 1, 1, 1, 1, 1, 1},
+                       {2, 1, 1, 0, 0, -1, -1, -2},
+                       {2, 1, -1, -2, -2, -1, 1, 2},
+                       {1, 0, -2, -1, 1, 2, 0, -1},
+                       {1, -1, -1, 1, 1, -1, -1, 1},
+                       {1, -2, 0, 1, -1, 0, 2, -1},
+                       {1, -2, 2, -1, -1, 2, -2, 1},
+                       {0, -1, 1, -2, 2, -1, 1, 0}}};
+
+constexpr Mat8 kRDCT = {{{1, 1, 1, 1, 1, 1, 1, 1},
+                         {1, 1, 1, 0, 0, -1, -1, -1},
+                         {1, 0, 0, -1, -1, 0, 0, 1},
+                         {1, 0, -1, -1, 1, 1, 0, -1},
+                         {1, -1, -1, 1, 1, -1, -1, 1},
+                         {1, -1, 0, 1, -1, 0, 1, -1},
+                         {0, -1, 1, 0, 0, 1, -1, 0},
+                         {0, -1, 1, -1, 1, -1, 1, 0}}};
+
+constexpr Mat8 kT4 = {{{1, 1, 1, 1, 1, 1, 1, 1},
+                       {1, 1, 1, 0, 0, -1, -1, -1},
+                       {1, 1, -1, -1, -1, -1, 1, 1},
+                       {1, 0, -1, -1, 1, 1, 0, -1},
+                       {1, -1, -1, 1, 1, -1, -1, 1},
+                       {1, -1, 0, 1, -1, 0, 1, -1},
+                       {1, -1, 1, -1, -1, 1, -1, 1},
+                       {0, -1, 1, -1, 1, -1, 1, 0}}};
+
+constexpr const Mat8 &builtin(int id) {
+    return id == ADCT_T1 ? kT1 : id == ADCT_T2 ? kT2 : id == ADCT_LO ? kLOx2
+         : id == ADCT_T6 ? kT6 : id == ADCT_RDCT ? kRDCT : kT4;
+}
+
+// JPEG zig-zag: kZZ[z] = 8*row + col of the z-th scanned coefficient.
+constexpr int kZZ[64] = {
+    0,  1,  8,  16, 9,  2,  3,  10, 17, 24, 32, 25, 18, 11, 4,  5,
+    12, 19, 26, 33, 40, 48, 41, 34, 27, 20, 13, 6,  7,  14, 21, 28,
+    35, 42, 49, 56, 57, 50, 43, 36, 29, 22, 15, 23, 30, 37, 44, 51,
+    58, 59, 52, 45, 38, 31, 39, 46, 53, 60, 61, 54, 47, 55, 62, 63};
+
+constexpr int zz_pos(int k, int l) {
+    for (int z = 0; z < 64; ++z)
+        if (kZZ[z] == 8 * k + l) return z;
+    return -1;
+}
+
+// Per-transform constants derived at compile time.
+template <int ID>
+struct Tf {
+    static constexpr const Mat8 &M = builtin(ID);
+    static constexpr int8_t t(int k, int m) { return M.m[k][m]; }
+    static constexpr int32_t n(int k) {
+        int32_t s = 0;
+        for (int m = 0; m < 8; ++m) s += int32_t(M.m[k][m]) * M.m[k][m];
+        return s;
+    }
+    static constexpr int32_t L1() {
+        int32_t l = 1;
+        for (int k = 0; k < 8; ++k) l = std::lcm(l, n(k));
+        return l;
+    }
+    static constexpr int32_t c(int k) { return L1() / n(k); }
+    static constexpr int32_t L() { return L1() * L1(); }
+    // |Y| fits int16 for 8-bit input (checked by the host bound routine too).
+    static constexpr bool kSymmetric() {
+        for (int k = 0; k < 8; ++k)
+            for (int m = 0; m < 4; ++m)
+                if (M.m[k][7 - m] != ((k & 1) ? -M.m[k][m] : M.m[k][m])) return false;
+        return true;
+    }
+    static_assert(kSymmetric(), "even rows symmetric, odd rows antisymmetric");
+};
+
+// ---------------------------------------------------------------- launch args
+
+constexpr int kMaxPlanes = 4;
+
+struct PlaneArg {
+    int64_t in_off;     // byte offset of the plane inside a frame (input)
+    int64_t out_off;    // byte offset inside an output frame
+    int32_t pitch_in;
+    int32_t pitch_out;
+    int32_t nbx;        // blocks per block-row
+    int32_t nblocks;    // blocks in the plane
+    int32_t wave_start; // first wave of this plane inside a frame
+    int32_t block_off;  // first block of this plane inside a frame
+};
+
+struct CodecArgs {
+    const uint8_t *in;
+    uint8_t *out;
+    int16_t *coef;
+    float *coef_f;
+    unsigned long long *sse;
+    int64_t fs_in;      // frame stride of `in` (bytes)
+    int64_t fs_out;     // frame stride of `out`
+    int32_t n_frames;
+    int32_t n_planes;
+    int32_t waves_per_frame;
+    int32_t blocks_per_frame;
+    int32_t r;
+    int32_t pad;
+    PlaneArg pl[kMaxPlanes];
+    float bscale[64];    // s_k s_l, natural order (for the float coefficients)
+    double qalpha[64];   // s_k s_l / step (irrational classes)
+    int32_t qden[64];    // 2 * step * sqrt(n_k n_l) for rational classes, else 0
+    float qinv[64];      // 1 / qden
+    double dq[64];       // step * s_k s_l (dequantisation straight into C_hat^T . C_hat)
+};
+
+enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2 };
+
+adct_status launch_codec(int tid, int band, bool quant, Mode mode, const CodecArgs &a,
+                         int total_waves, hipStream_t s);
+
+}  // namespace adct

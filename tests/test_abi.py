@@ -1,0 +1,119 @@
+"""The C ABI library loads, exports every declared symbol, and validates its
+arguments on the host (no GPU work is started by any call here)."""
+
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1808_02950_amd as A
+from oracle import codec as Co
+from oracle import matrices as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(adct_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    lib = A.lib()
+    names = _declared()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("name", ["T1", "T2", "LO", "T6", "RDCT", "T4"])
+def test_builtin_matrices_match_oracle(name):
+    assert np.array_equal(A.matrix_get(name), M.TRANSFORMS[name])
+
+
+def test_forward_bound_matches_interval_propagation():
+    assert A.transform_bounds("T1", 10)[0] == 18360
+    assert A.transform_bounds("LO", 10)[0] == 65280
+
+
+@pytest.mark.parametrize("name,r", [("T1", 10), ("T1", 3), ("RDCT", 10), ("LO", 21)])
+def test_inverse_bound_is_attained(name, r):
+    # the library's bound on the exact inverse numerator is the maximum over
+    # 8-bit blocks: the extremal block (255 where the kernel is positive, 0
+    # elsewhere) reaches it in the oracle's exact inverse
+    t = M.TRANSFORMS[name]
+    bound = A.transform_bounds(name, r)[1]
+    n = M.row_norms2(t)
+    best = 0
+    mask = Co.zonal_mask(r)
+    for x in range(8):
+        for y in range(8):
+            for sign in (1, -1):
+                # sign pattern of d num(x, y) / d A(u, v)
+                e = np.zeros((64, 8, 8), dtype=np.int64)
+                for u in range(8):
+                    for v in range(8):
+                        e[8 * u + v, u, v] = 1
+                yk = Co.forward_int(e, t) * mask
+                num, _ = Co.inverse_exact(yk, t)
+                g = num[:, x, y]
+                blk = np.where(sign * g > 0, 255, 0).reshape(1, 8, 8)
+                yy = Co.forward_int(blk, t) * mask
+                nn, _ = Co.inverse_exact(yy, t)
+                best = max(best, abs(int(nn[0, x, y])))
+    assert best == bound
+
+
+def _call(fn, *args):
+    return getattr(A.lib(), fn)(*args)
+
+
+FAKE = ctypes.c_void_p(4096)          # never dereferenced: every case fails validation
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((None, 8, 8, 8, A.T1, None, 10, 0, FAKE, None, None), -1),         # null image
+    ((FAKE, 8, 8, 8, A.T1, None, 10, 0, None, None, None), -1),         # no output
+    ((FAKE, 12, 8, 8, A.T1, None, 10, 0, FAKE, None, None), -2),        # H % 8
+    ((FAKE, 8, 16, 8, A.T1, None, 10, 0, FAKE, None, None), -2),        # pitch < W
+    ((FAKE, 8, 8, 12, A.T1, None, 10, 0, FAKE, None, None), -2),        # pitch % 8
+    ((FAKE, 8, 8, 8, A.T1, None, 0, 0, FAKE, None, None), -3),          # r = 0
+    ((FAKE, 8, 8, 8, A.T1, None, 65, 0, FAKE, None, None), -3),         # r = 65
+    ((FAKE, 8, 8, 8, A.T1, None, 10, -1, FAKE, None, None), -3),        # step < 0
+    ((FAKE, 8, 8, 8, A.LO, None, 10, 0, FAKE, None, None), -4),         # LO into int16
+    ((FAKE, 8, 8, 8, 42, None, 10, 0, FAKE, None, None), -1),           # unknown id
+    ((FAKE, 8, 8, 8, A.T1, None, 10, 5, FAKE, None, None), -7),         # step with exact ties
+    ((FAKE, 8, 8, 8, A.T1, None, 10, 12, FAKE, None, None), -7),
+    ((FAKE, 8, 8, 8, A.LO, None, 10, 16, FAKE, None, None), -7),
+])
+def test_encode_argument_errors(args, expect):
+    assert _call("adct_encode_blocks", *args) == expect
+    assert A.lib().adct_last_error()
+
+
+def test_stream_argument_errors():
+    planes = A.planes_struct([(0, 16, 16, 16)])
+    sse = ctypes.c_void_p(8192)
+    lib = A.lib()
+    assert lib.adct_evaluate_stream(FAKE, 256, 0, planes, 1, A.T1, None, 10, 0, None, None, 0, sse, None) == -3
+    assert lib.adct_evaluate_stream(FAKE, 256, 1, planes, 5, A.T1, None, 10, 0, None, None, 0, sse, None) == -3
+    assert lib.adct_evaluate_stream(FAKE, 256, 1, planes, 1, A.T1, None, 10, 0, None, None, 0, None, None) == -1
+    bad = A.planes_struct([(4, 16, 16, 16)])
+    assert lib.adct_evaluate_stream(FAKE, 256, 1, bad, 1, A.T1, None, 10, 0, None, None, 0, sse, None) == -2
+
+
+def test_tie_free_quantiser_steps_accepted():
+    lib = A.lib()
+    for tid, step in [(A.T1, 8), (A.T1, 16), (A.T1, 24), (A.T4, 8), (A.T6, 40), (A.LO, 32)]:
+        assert lib.adct_check_codec_args(tid, None, 10, step, 1) == 0
+    for tid, step in [(A.T1, 4), (A.T2, 20), (A.LO, 16), (A.RDCT, 6)]:
+        assert lib.adct_check_codec_args(tid, None, 10, step, 1) == -7
+    assert lib.adct_check_codec_args(A.LO, None, 10, 0, 1) == -4
+    assert lib.adct_check_codec_args(A.LO, None, 10, 0, 0) == 0
