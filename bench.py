@@ -68,6 +68,20 @@ def cpu_baseline(spec, n_frames: int, r: int, step: int):
                       f"T1 r={r} step {step}, encode+decode+SSE, one thread, {dt:.1f} s"}
 
 
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs, or None when the kernel sources changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "codec_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +90,9 @@ def main():
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--cpu-frames", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="resident workgroups per CU of the codec grid (0 = occupancy limit, "
+                         "-1 = one tile per wave)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the codec shards by frame "
@@ -91,6 +108,7 @@ def main():
     r, step = 10, 16
     dev = torch.device("cuda:0")
     A.lib()
+    A.codec_set_schedule(args.schedule)
     spec = video_spec(n_frames=args.frames)
     log(f"building {spec.n_frames} frames of {spec.width}x{spec.height} 4:2:0 on the GPU")
     frames = build_stream(spec, dev)
@@ -148,13 +166,13 @@ def main():
         "dtype": "int32/f64",
         "data": "synthetic",
         "config": {"workload": f"video stream {spec.n_frames} frames 3840x2160 YUV 4:2:0 uint8",
-                   "transform": "T1", "r": r, "quant_step": step,
+                   "transform": "T1", "r": r, "quant_step": step, "schedule": args.schedule,
                    "samples_per_frame": spec.frame_bytes, "blocks_per_launch": blocks},
         "psnr_db": {"T1_frame_mean": round(psnr_frame, 4),
                     "T1_Y": round(psnr_planes[0], 4), "T1_U": round(psnr_planes[1], 4),
                     "T1_V": round(psnr_planes[2], 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
                      "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:

@@ -90,6 +90,12 @@ const char *adct_last_error(void);
 /* ABI version of this header (major * 100 + minor). */
 int adct_version(void);
 
+/* Launch schedule of the codec kernels (process-wide): the number of resident
+ * 4-wave workgroups per compute unit of the persistent grid.  0 (default) =
+ * as many as occupancy allows; -1 = no persistence (one 64-block tile per
+ * wave); k > 0 = at most k.  Results do not depend on it. */
+adct_status adct_codec_set_schedule(int workgroups_per_cu);
+
 /* Fill *out with a built-in matrix (not ADCT_DCT / ADCT_CUSTOM).  Host only. */
 adct_status adct_matrix_get(adct_transform_id id, adct_matrix *out);
 

@@ -53,6 +53,7 @@ _SIGNATURES = {
     "adct_last_error": (ctypes.c_char_p, []),
     "adct_version": (_I, []),
     "adct_matrix_get": (_I, [_I, ctypes.POINTER(Matrix)]),
+    "adct_codec_set_schedule": (_I, [_I]),
     "adct_check_codec_args": (_I, [_I, ctypes.POINTER(Matrix), _I, _I, _I]),
     "adct_transform_bounds": (_I, [_I, ctypes.POINTER(Matrix), _I, _I,
                                    ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -112,6 +113,12 @@ def _need_cuda(t, dtype, name):
 
 def version() -> int:
     return lib().adct_version()
+
+
+def codec_set_schedule(workgroups_per_cu: int) -> None:
+    """adct_codec_set_schedule: 0 = occupancy-limited persistent grid,
+    -1 = one tile per wave, k > 0 = at most k workgroups per CU."""
+    _check(lib().adct_codec_set_schedule(int(workgroups_per_cu)))
 
 
 def matrix_get(t) -> np.ndarray:

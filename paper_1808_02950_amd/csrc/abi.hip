@@ -10,6 +10,9 @@
 namespace adct {
 
 static thread_local std::string g_err;
+static int g_codec_wgs_per_cu = 0;
+
+int codec_wgs_per_cu() { return g_codec_wgs_per_cu; }
 
 void set_error(const std::string &msg) { g_err = msg; }
 
@@ -151,27 +154,17 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
     }
     for (int k = 0; k < 8; ++k)
         for (int l = 0; l < 8; ++l) {
-            const int i = 8 * k + l;
             const int64_t prod = int64_t(n[k]) * n[l];
-            const double sks = 1.0 / sqrt(double(prod));
-            a->bscale[i] = float(sks);
-            a->dq[i] = double(quant_step) * sks;
-            a->qden[i] = 0;
-            a->qinv[i] = 0.f;
-            a->qalpha[i] = 0.0;
-            if (out->quant) {
-                const int64_t mu = int64_t(llround(sqrt(double(prod))));
-                if (mu * mu == prod) {
-                    const int64_t d2 = 2 * int64_t(quant_step) * mu;
-                    if (2 * fb + d2 >= (int64_t(1) << 24) || d2 >= (int64_t(1) << 23))
-                        return fail(ADCT_ERANGE, "quant_step too large for the exact integer quantiser");
-                    a->qden[i] = int32_t(d2);
-                    a->qinv[i] = float(1.0 / double(d2));
-                } else {
-                    a->qalpha[i] = sks / double(quant_step);
-                }
+            const int64_t mu = int64_t(llround(sqrt(double(prod))));
+            if (out->quant && mu * mu == prod) {
+                const int64_t d2 = 2 * int64_t(quant_step) * mu;
+                if (2 * fb + d2 >= (int64_t(1) << 24) || d2 >= (int64_t(1) << 23))
+                    return fail(ADCT_ERANGE, "quant_step too large for the exact integer quantiser");
             }
         }
+    a->step = quant_step;
+    a->inv_step_f = quant_step ? float(1.0 / quant_step) : 0.f;
+    a->inv_step_d = quant_step ? 1.0 / quant_step : 0.0;
     return ADCT_OK;
 }
 
@@ -183,6 +176,8 @@ adct_status check_plane(const void *base, int64_t offset, int H, int W, int pitc
         return fail(ADCT_EDIM, std::string(what) + ": base, offsets and pitch must be 8-byte aligned");
     if (int64_t(H / 8) * (W / 8) > (int64_t(1) << 30))
         return fail(ADCT_EDIM, std::string(what) + ": too many blocks");
+    if (pitch >= (1 << 24) || int64_t(H) * pitch >= (int64_t(1) << 32))
+        return fail(ADCT_EDIM, std::string(what) + ": plane larger than 4 GiB or pitch >= 2^24");
     return ADCT_OK;
 }
 
@@ -262,6 +257,13 @@ extern "C" {
 const char *adct_last_error(void) { return g_err.c_str(); }
 
 int adct_version(void) { return 100; }
+
+adct_status adct_codec_set_schedule(int workgroups_per_cu) {
+    if (workgroups_per_cu < -1 || workgroups_per_cu > 64)
+        return fail(ADCT_ERANGE, "workgroups_per_cu must be in [-1, 64]");
+    g_codec_wgs_per_cu = workgroups_per_cu;
+    return ADCT_OK;
+}
 
 adct_status adct_matrix_get(adct_transform_id id, adct_matrix *out) {
     if (!out) return fail(ADCT_EINVAL, "out is null");

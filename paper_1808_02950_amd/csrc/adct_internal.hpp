@@ -122,6 +122,28 @@ struct Tf {
         return l;
     }
     static constexpr int32_t c(int k) { return L1() / n(k); }
+    struct Tables {
+        int32_t mu[64];   // mu with mu^2 = n_k n_l, or 0 when n_k n_l is not a square
+        double skl[64];   // s_k s_l = 1 / sqrt(n_k n_l)
+    };
+    static constexpr Tables make_tables() {
+        Tables t{};
+        for (int k = 0; k < 8; ++k)
+            for (int l = 0; l < 8; ++l) {
+                const int32_t v = n(k) * n(l);
+                int32_t m = 0;
+                for (int32_t c = 1; c * c <= v; ++c)
+                    if (c * c == v) m = c;
+                t.mu[8 * k + l] = m;
+                double r = double(v);               // Newton iteration for sqrt(v)
+                for (int i = 0; i < 64; ++i) r = 0.5 * (r + double(v) / r);
+                t.skl[8 * k + l] = 1.0 / r;
+            }
+        return t;
+    }
+    static constexpr Tables kTab = make_tables();
+    static constexpr int32_t mu(int k, int l) { return kTab.mu[8 * k + l]; }
+    static constexpr double skl(int k, int l) { return kTab.skl[8 * k + l]; }
     static constexpr int32_t L() { return L1() * L1(); }
     // |Y| fits int16 for 8-bit input (checked by the host bound routine too).
     static constexpr bool kSymmetric() {
@@ -163,14 +185,16 @@ struct CodecArgs {
     int32_t r;
     int32_t pad;
     PlaneArg pl[kMaxPlanes];
-    float bscale[64];    // s_k s_l, natural order (for the float coefficients)
-    double qalpha[64];   // s_k s_l / step (irrational classes)
-    int32_t qden[64];    // 2 * step * sqrt(n_k n_l) for rational classes, else 0
-    float qinv[64];      // 1 / qden
-    double dq[64];       // step * s_k s_l (dequantisation straight into C_hat^T . C_hat)
+    int32_t step;        // quantiser step (0: zonal coding only)
+    float inv_step_f;    // 1 / step
+    double inv_step_d;   // 1 / step
 };
 
 enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2 };
+
+// Codec launch schedule: resident 4-wave workgroups per CU (0 = as many as
+// occupancy allows, -1 = one tile per wave, no persistence).
+int codec_wgs_per_cu();
 
 adct_status launch_codec(int tid, int band, bool quant, Mode mode, const CodecArgs &a,
                          int total_waves, hipStream_t s);

@@ -4,6 +4,9 @@
 // so both 1-D passes and the transpose between them stay in registers; a
 // wave covers 64 consecutive blocks of a plane in raster order and every row
 // load / store of the wave is one contiguous 512-byte run.
+#include <algorithm>
+#include <type_traits>
+
 #include "adct_internal.hpp"
 
 namespace adct {
@@ -57,24 +60,61 @@ __device__ __forceinline__ void fwd8(const V (&x)[8], V (&y)[8]) {
     }
 }
 
+// acc + c v for a small constant c (0, +-1, +-2); float64 uses one fma.
+template <class V>
+__device__ __forceinline__ V mac(V acc, V v, int c) {
+    if constexpr (std::is_same<V, double>::value) {
+        if (c == 1) return acc + v;
+        if (c == -1) return acc - v;
+        return fma(v, double(c), acc);
+    } else {
+        if (c == 1) return acc + v;
+        if (c == -1) return acc - v;
+        if (c == 2) return acc + (v + v);
+        return acc - (v + v);
+    }
+}
+
+template <class V>
+__device__ __forceinline__ V cmul(V v, int c) {
+    if (c == 1) return v;
+    if (c == -1) return -v;
+    return v * V(c);
+}
+
 // Inverse 8-point transform x = T^T y when only y[0..K) can be nonzero:
 // x_m = e_m + o_m, x_{7-m} = e_m - o_m with e from the even rows, o from the odd.
 template <int ID, int K, class V>
-__device__ __forceinline__ void inv8(const V (&y)[8], V (&x)[8]) {
+__device__ __forceinline__ void inv8(const V (&y)[8], V (&x)[8], int kmax = K - 1) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         V e = V(0), o = V(0);
+        bool he = false, ho = false;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int c = Tf<ID>::t(k, m);
-            V &acc = (k & 1) ? o : e;
-            if (c == 1) acc = acc + y[k];
-            else if (c == -1) acc = acc - y[k];
-            else if (c == 2) acc = acc + (y[k] + y[k]);
-            else if (c == -2) acc = acc - (y[k] + y[k]);
+            if (c == 0 || k > kmax) continue;
+            if (k & 1) {
+                o = ho ? mac(o, y[k], c) : cmul(y[k], c);
+                ho = true;
+            } else {
+                e = he ? mac(e, y[k], c) : cmul(y[k], c);
+                he = true;
+            }
         }
-        x[m] = e + o;
-        x[7 - m] = e - o;
+        if (he && ho) {
+            x[m] = e + o;
+            x[7 - m] = e - o;
+        } else if (he) {
+            x[m] = e;
+            x[7 - m] = e;
+        } else if (ho) {
+            x[m] = o;
+            x[7 - m] = -o;
+        } else {
+            x[m] = V(0);
+            x[7 - m] = V(0);
+        }
     }
 }
 
@@ -91,30 +131,37 @@ __device__ __forceinline__ int rne_div_clip(int n) {
     return int(q) - int(tie & (q & 1u));
 }
 
-__device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
-    return uint32_t(a) | (uint32_t(b) << 8) | (uint32_t(c) << 16) | (uint32_t(d) << 24);
-}
-
 __device__ __forceinline__ int byte_of(uint32_t w, int i) { return int((w >> (8 * i)) & 0xffu); }
 
-// round-half-away(Y / d) for the rational classes: floor((2|Y| + d) / (2d)) with
-// qden = 2d, exact for 2|Y| + d < 2^24 (float estimate, integer correction).
-__device__ __forceinline__ int quant_rational(int y, int32_t qden, float qinv) {
+// round-half-to-even of a float64 to int32 (|x| < 2^31): adding 1.5 * 2^52
+// leaves the rounded integer in the low word of the sum.
+__device__ __forceinline__ int rne_i32(double x) {
+    return __double2loint(x + 6755399441055744.0);
+}
+
+__device__ __forceinline__ int clamp255(int v) { return min(max(v, 0), 255); }
+
+// round-half-away(Y / d), d = step * mu, for the classes where n_k n_l = mu^2
+// (Y / d can be an exact half): floor((2|Y| + d) / (2d)) from a float estimate
+// corrected in exact integer arithmetic (2|Y| + d < 2^24 is checked on the host).
+__device__ __forceinline__ int quant_rational(int y, int step, int mu, float inv_2mu, float inv_step) {
     const int ay = y < 0 ? -y : y;
-    const int num = 2 * ay + (qden >> 1);
-    int q = int(float(num) * qinv);
-    const int rem = num - __mul24(q, qden);
-    q += (rem >= qden) ? 1 : 0;
+    const int d = step * mu;                                  // wave-uniform
+    const int d2 = d + d;
+    const int num = 2 * ay + d;
+    int q = int(float(num) * inv_2mu * inv_step);
+    const int rem = num - __mul24(q, d2);
+    q += (rem >= d2) ? 1 : 0;
     q -= (rem < 0) ? 1 : 0;
     return y < 0 ? -q : q;
 }
 
-// round-half-away(Y * alpha) for irrational classes (never an exact half; the
-// nearest half is > 1e-9 away for |Y| < 2^16, far above the float64 error).
-__device__ __forceinline__ int quant_irrational(int y, double alpha) {
-    const double x = double(y < 0 ? -y : y) * alpha;
-    const int q = int(floor(x + 0.5));
-    return y < 0 ? -q : q;
+// round-half-away(Y s_k s_l / step) where s_k s_l = 1/sqrt(n_k n_l) is
+// irrational: the quotient is never an exact half (its nearest half is > 1e-9
+// away for |Y| < 2^16, far above the float64 error), so round-half-to-even of
+// the float64 product gives the same integer.
+__device__ __forceinline__ int quant_irrational(int y, double skl, double inv_step) {
+    return rne_i32(double(y) * skl * inv_step);
 }
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
@@ -128,37 +175,90 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v) {
 // BAND: only coefficients (k, l) with k + l <= BAND can be retained (r <= 10
 // needs BAND 3; 14 is the whole block).  The retained set inside the band is
 // the zig-zag prefix of length r (runtime).
+//
+// The grid is persistent: each wave walks tiles gw, gw + stride, ... (a tile is
+// 64 consecutive blocks of one plane of one frame) and issues the loads of its
+// next tile before it transforms the current one.
 
-template <int ID, int BAND, bool QUANT, int MODE>
-__global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
-    constexpr int KB = BAND + 1 < 8 ? BAND + 1 : 8;  // rows / columns touched
-    const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (gw >= a.n_frames * a.waves_per_frame) return;  // whole wave leaves
-    const int f = gw / a.waves_per_frame;
-    const int w = gw - f * a.waves_per_frame;
+struct Tile {
+    int f, p;            // frame, plane (wave-uniform)
+    int b;               // block index inside the plane (per lane)
+    bool active;
+    uint32_t in_off, out_off;
+};
+
+__device__ __forceinline__ Tile tile_of(const CodecArgs &a, int gw, int lane) {
+    Tile t;
+    t.f = gw / a.waves_per_frame;
+    const int w = gw - t.f * a.waves_per_frame;
     int p = 0;
     while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
-    const PlaneArg P = a.pl[p];
-    const int b = (w - P.wave_start) * 64 + lane;
-    const bool active = b < P.nblocks;
-    const int by = active ? b / P.nbx : 0;
-    const int bx = active ? b - by * P.nbx : 0;
-    const int64_t gblk = int64_t(f) * a.blocks_per_frame + P.block_off + b;
-
-    // ---- pixels in (8 bytes per row) --------------------------------------
-    uint32_t pix[8][2];
-    if constexpr (MODE != kDecode) {
-        const uint8_t *src = a.in + int64_t(f) * a.fs_in + P.in_off +
-                             int64_t(8 * by) * P.pitch_in + 8 * bx;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            u32x2 v = {0u, 0u};
-            if (active) v = __builtin_nontemporal_load((const u32x2 *)(src + int64_t(x) * P.pitch_in));
-            pix[x][0] = v.x;
-            pix[x][1] = v.y;
+    t.p = p;
+    const PlaneArg &P = a.pl[p];
+    const int b0 = (w - P.wave_start) * 64;             // first block of the wave
+    const int by0 = b0 / P.nbx;
+    const int bx0 = b0 - by0 * P.nbx;
+    t.b = b0 + lane;
+    t.active = t.b < P.nblocks;
+    int by, bx;
+    if (P.nbx >= 64) {                                   // at most one row change
+        bx = bx0 + lane;
+        by = by0;
+        if (bx >= P.nbx) {
+            bx -= P.nbx;
+            ++by;
         }
+    } else {
+        by = t.b / P.nbx;
+        bx = t.b - by * P.nbx;
     }
+    if (!t.active) by = bx = 0;
+    t.in_off = __umul24(uint32_t(8 * by), uint32_t(P.pitch_in)) + uint32_t(8 * bx);
+    t.out_off = __umul24(uint32_t(8 * by), uint32_t(P.pitch_out)) + uint32_t(8 * bx);
+    return t;
+}
+
+__device__ __forceinline__ void load_tile(const CodecArgs &a, const Tile &t, uint32_t (&pix)[8][2]) {
+    const PlaneArg &P = a.pl[t.p];
+    const uint8_t *src = a.in + int64_t(t.f) * a.fs_in + P.in_off + t.in_off;
+    // inactive lanes point at block (0, 0) of the plane: the load stays in
+    // bounds and its result is never stored or scored
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const u32x2 v = __builtin_nontemporal_load((const u32x2 *)(src + x * P.pitch_in));
+        pix[x][0] = v.x;
+        pix[x][1] = v.y;
+    }
+}
+
+// Pack a reconstructed row (q in [0, 255]) into bytes and accumulate the two
+// dot-product sums whose combination is the squared error:
+// sum (q - a)^2 = [sum q^2 + sum a^2] - 2 sum q a.
+__device__ __forceinline__ u32x2 emit_row(const int (&q)[8], uint32_t w0, uint32_t w1,
+                                          uint32_t &sq, uint32_t &cross) {
+    const uint32_t r01 = uint32_t(q[0]) | (uint32_t(q[1]) << 16);
+    const uint32_t r23 = uint32_t(q[2]) | (uint32_t(q[3]) << 16);
+    const uint32_t r45 = uint32_t(q[4]) | (uint32_t(q[5]) << 16);
+    const uint32_t r67 = uint32_t(q[6]) | (uint32_t(q[7]) << 16);
+    u32x2 out;
+    out.x = __builtin_amdgcn_perm(r23, r01, 0x06040200u);
+    out.y = __builtin_amdgcn_perm(r67, r45, 0x06040200u);
+    sq = __builtin_amdgcn_udot4(out.x, out.x, sq, false);
+    sq = __builtin_amdgcn_udot4(out.y, out.y, sq, false);
+    sq = __builtin_amdgcn_udot4(w0, w0, sq, false);
+    sq = __builtin_amdgcn_udot4(w1, w1, sq, false);
+    cross = __builtin_amdgcn_udot4(out.x, w0, cross, false);
+    cross = __builtin_amdgcn_udot4(out.y, w1, cross, false);
+    return out;
+}
+
+template <int ID, int BAND, bool QUANT, int MODE>
+__device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
+                                             const uint32_t (&pix)[8][2]) {
+    constexpr int KB = BAND + 1 < 8 ? BAND + 1 : 8;  // rows / columns touched
+    const PlaneArg &P = a.pl[t.p];
+    const bool active = t.active;
+    const int64_t gblk = int64_t(t.f) * a.blocks_per_frame + P.block_off + t.b;
 
     // ---- coefficients inside the band --------------------------------------
     int Y[8][8];  // Y[k][l] (only k + l <= BAND meaningful)
@@ -200,15 +300,23 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
             const int k = kZZ[z] >> 3, l = kZZ[z] & 7;
             int v = Y[k][l];
             if constexpr (QUANT) {
-                const int i = kZZ[z];
-                v = a.qden[i] ? quant_rational(v, a.qden[i], a.qinv[i])
-                              : quant_irrational(v, a.qalpha[i]);
+                const int mu = Tf<ID>::mu(k, l);
+                v = mu ? quant_rational(v, a.step, mu, float(0.5 / mu), a.inv_step_f)
+                       : quant_irrational(v, Tf<ID>::skl(k, l), a.inv_step_d);
             }
             C[k][l] = (z < a.r) ? v : 0;
         }
         if (active && a.coef) {
             int16_t *dst = a.coef + gblk * a.r;
-            if ((a.r & 1) == 0) {
+            if (a.r == NZ && (NZ & 1) == 0) {             // whole band, no per-entry test
+#pragma unroll
+                for (int z = 0; z < NZ; z += 2) {
+                    const int k0 = kZZ[z] >> 3, l0 = kZZ[z] & 7;
+                    const int k1 = kZZ[z + 1] >> 3, l1 = kZZ[z + 1] & 7;
+                    const uint32_t pk = (uint32_t(C[k0][l0]) & 0xffffu) | (uint32_t(C[k1][l1]) << 16);
+                    __builtin_nontemporal_store(pk, (uint32_t *)(dst + z));
+                }
+            } else if ((a.r & 1) == 0) {
 #pragma unroll
                 for (int z = 0; z < NZ; z += 2) {
                     if (z + 1 < a.r) {
@@ -228,7 +336,9 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
             float *dst = a.coef_f + gblk * a.r;
 #pragma unroll
             for (int z = 0; z < NZ; ++z)
-                if (z < a.r) dst[z] = float(Y[kZZ[z] >> 3][kZZ[z] & 7]) * a.bscale[kZZ[z]];
+                if (z < a.r)
+                    dst[z] = float(Y[kZZ[z] >> 3][kZZ[z] & 7]) *
+                             float(Tf<ID>::skl(kZZ[z] >> 3, kZZ[z] & 7));
         }
     } else {
         if (active) {
@@ -242,10 +352,8 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
     if constexpr (MODE == kEncode) return;
 
     // ---- inverse, round, clip, store, squared error ------------------------
-    uint8_t *dst = a.out ? a.out + int64_t(f) * a.fs_out + P.out_off +
-                               int64_t(8 * by) * P.pitch_out + 8 * bx
-                         : nullptr;
-    unsigned err = 0;
+    uint8_t *dst = a.out ? a.out + int64_t(t.f) * a.fs_out + P.out_off + t.out_off : nullptr;
+    uint32_t sq = 0, cross = 0;
     if constexpr (!QUANT) {
         // exact: A L = T^T (Y o c c^T) T with c_k = L1 / n_k, L = L1^2
         constexpr int32_t L = Tf<ID>::L();
@@ -256,7 +364,7 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 yin[k] = (k < KB) ? __mul24(C[k][l], Tf<ID>::c(k) * Tf<ID>::c(l)) : 0;
-            inv8<ID, KB>(yin, xo);
+            inv8<ID, KB>(yin, xo, BAND - l);
 #pragma unroll
             for (int x = 0; x < 8; ++x) U[x][l] = xo[x];
         }
@@ -269,17 +377,9 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
             int q[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) q[m] = rne_div_clip<L>(xo[m]);
-            if constexpr (MODE == kEvaluate) {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int d = q[m] - byte_of(pix[x][m >> 2], m & 3);
-                    err += unsigned(__mul24(d, d));
-                }
-            }
-            if (active && dst) {
-                const u32x2 v = {pack4(q[0], q[1], q[2], q[3]), pack4(q[4], q[5], q[6], q[7])};
-                __builtin_nontemporal_store(v, (u32x2 *)(dst + int64_t(x) * P.pitch_out));
-            }
+            const u32x2 v = emit_row(q, MODE == kEvaluate ? pix[x][0] : 0u,
+                                     MODE == kEvaluate ? pix[x][1] : 0u, sq, cross);
+            if (active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + x * P.pitch_out));
         }
     } else {
         // dequantised B = step q, A = C_hat^T B C_hat in float64
@@ -289,8 +389,9 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
             double yin[8], xo[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                yin[k] = (k < KB) ? double(C[k][l]) * a.dq[8 * k + l] : 0.0;
-            inv8<ID, KB>(yin, xo);
+                yin[k] = (k < KB && k + l <= BAND)
+                             ? double(C[k][l] * a.step) * Tf<ID>::skl(k, l) : 0.0;
+            inv8<ID, KB>(yin, xo, BAND - l);
 #pragma unroll
             for (int x = 0; x < 8; ++x) U[x][l] = xo[x];
         }
@@ -302,36 +403,92 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
             inv8<ID, KB>(yin, xo);
             int q[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) q[m] = int(fmin(fmax(rint(xo[m]), 0.0), 255.0));
-            if constexpr (MODE == kEvaluate) {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int d = q[m] - byte_of(pix[x][m >> 2], m & 3);
-                    err += unsigned(__mul24(d, d));
-                }
-            }
-            if (active && dst) {
-                const u32x2 v = {pack4(q[0], q[1], q[2], q[3]), pack4(q[4], q[5], q[6], q[7])};
-                __builtin_nontemporal_store(v, (u32x2 *)(dst + int64_t(x) * P.pitch_out));
-            }
+            for (int m = 0; m < 8; ++m) q[m] = clamp255(rne_i32(xo[m]));
+            const u32x2 v = emit_row(q, MODE == kEvaluate ? pix[x][0] : 0u,
+                                     MODE == kEvaluate ? pix[x][1] : 0u, sq, cross);
+            if (active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + x * P.pitch_out));
         }
     }
 
     if constexpr (MODE == kEvaluate) {
-        if (!active) err = 0;
-        err = wave_sum(err);
-        if (lane == 0 && err) atomicAdd(a.sse + int64_t(f) * a.n_planes + p, (unsigned long long)err);
+        unsigned e = active ? sq - 2u * cross : 0u;
+        e = wave_sum(e);
+        if ((threadIdx.x & 63) == 0 && e)
+            atomicAdd(a.sse + int64_t(t.f) * a.n_planes + t.p, (unsigned long long)e);
     }
+}
+
+template <int ID, int BAND, bool QUANT, int MODE>
+__global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int total = a.n_frames * a.waves_per_frame;
+    const int stride = int(gridDim.x) * 4;
+    int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (gw >= total) return;                               // whole wave leaves
+    // two pixel buffers used in turn: the next tile loads into one while the
+    // current tile is transformed from the other
+    uint32_t pa[8][2], pb[8][2];
+    Tile ta = tile_of(a, gw, lane), tb = ta;
+    if constexpr (MODE != kDecode) load_tile(a, ta, pa);
+    while (true) {
+        int nxt = gw + stride;
+        bool more = nxt < total;                           // wave-uniform
+        if (more) {
+            tb = tile_of(a, nxt, lane);
+            if constexpr (MODE != kDecode) load_tile(a, tb, pb);
+        }
+        process_tile<ID, BAND, QUANT, MODE>(a, ta, pa);
+        if (!more) break;
+        gw = nxt;
+        nxt = gw + stride;
+        more = nxt < total;
+        if (more) {
+            ta = tile_of(a, nxt, lane);
+            if constexpr (MODE != kDecode) load_tile(a, ta, pa);
+        }
+        process_tile<ID, BAND, QUANT, MODE>(a, tb, pb);
+        if (!more) break;
+        gw = nxt;
+    }
+}
+
+// Persistent grid: as many 4-wave workgroups as the device keeps resident
+// (occupancy x CUs), never more than there are tiles.
+template <class K>
+adct_status persistent_grid(K kernel, int total_waves, int *grid) {
+    static thread_local int cached_dev = -1, cus = 0;
+    int dev = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    if (dev != cached_dev) {
+        ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cached_dev = dev;
+    }
+    int per_cu = 0;
+    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+    if (per_cu < 1) per_cu = 1;
+    const int knob = codec_wgs_per_cu();
+    if (knob > 0) per_cu = std::min(per_cu, knob);
+    const int64_t want = (int64_t(total_waves) + 3) / 4;
+    *grid = knob < 0 ? int(want) : int(std::min<int64_t>(want, int64_t(per_cu) * cus));
+    return ADCT_OK;
+}
+
+template <int ID, int BAND, bool QUANT, int M>
+adct_status launch_one(const CodecArgs &a, int total_waves, hipStream_t s) {
+    auto kern = k_codec<ID, BAND, QUANT, M>;
+    int grid = 0;
+    adct_status st = persistent_grid(kern, total_waves, &grid);
+    if (st) return st;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, a);
+    ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
 }
 
 template <int ID, int BAND, bool QUANT>
 adct_status launch_mode(Mode mode, const CodecArgs &a, int total_waves, hipStream_t s) {
-    const dim3 grid((total_waves + 3) / 4), block(256);
-    if (mode == kEncode) hipLaunchKernelGGL((k_codec<ID, BAND, QUANT, kEncode>), grid, block, 0, s, a);
-    else if (mode == kDecode) hipLaunchKernelGGL((k_codec<ID, BAND, QUANT, kDecode>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_codec<ID, BAND, QUANT, kEvaluate>), grid, block, 0, s, a);
-    ADCT_HIP(hipGetLastError());
-    return ADCT_OK;
+    if (mode == kEncode) return launch_one<ID, BAND, QUANT, kEncode>(a, total_waves, s);
+    if (mode == kDecode) return launch_one<ID, BAND, QUANT, kDecode>(a, total_waves, s);
+    return launch_one<ID, BAND, QUANT, kEvaluate>(a, total_waves, s);
 }
 
 template <int ID>
