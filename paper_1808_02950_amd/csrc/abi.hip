@@ -203,6 +203,42 @@ int setup_planes(CodecArgs *a, const adct_plane *pl, int np) {
     return waves;
 }
 
+// Exact-DCT launch set-up: 16-block tiles per wave.
+int setup_dct(DctArgs *a, const adct_plane *pl, int np, int r, int step) {
+    int waves = 0, blocks = 0;
+    for (int p = 0; p < np; ++p) {
+        PlaneArg &d = a->pl[p];
+        d.in_off = pl[p].offset;
+        d.out_off = pl[p].offset;
+        d.pitch_in = pl[p].pitch;
+        d.pitch_out = pl[p].pitch;
+        d.nbx = pl[p].W / 8;
+        d.nblocks = (pl[p].H / 8) * (pl[p].W / 8);
+        d.wave_start = waves;
+        d.block_off = blocks;
+        waves += (d.nblocks + 15) / 16;
+        blocks += d.nblocks;
+    }
+    a->n_planes = np;
+    a->blocks_per_frame = blocks;
+    a->waves_per_frame = waves;
+    a->r = r;
+    a->step = step;
+    a->inv_step = step ? float(1.0 / step) : 0.f;
+    for (int k = 0; k < 8; ++k)
+        for (int x = 0; x < 8; ++x) {
+            const double alpha = k == 0 ? sqrt(0.125) : 0.5;
+            a->C[8 * k + x] = float(alpha * cos((2 * x + 1) * k * M_PI / 16.0));
+        }
+    return waves;
+}
+
+adct_status check_dct_args(int r, int quant_step) {
+    if (r < 1 || r > 64) return fail(ADCT_ERANGE, "r must be in [1, 64]");
+    if (quant_step < 0 || quant_step > 65535) return fail(ADCT_ERANGE, "quant_step must be in [0, 65535]");
+    return ADCT_OK;
+}
+
 }  // namespace
 }  // namespace adct
 
@@ -225,6 +261,30 @@ static adct_status stream_impl(const uint8_t *frames, int64_t frame_stride, int 
     for (int p = 0; p < n_planes; ++p) {
         adct_status st = check_plane(frames, planes[p].offset, planes[p].H, planes[p].W, planes[p].pitch, "plane");
         if (st) return st;
+    }
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (t == ADCT_DCT) {
+        adct_status st = check_dct_args(r, quant_step);
+        if (st) return st;
+        if (coef && quant_step == 0)
+            return fail(ADCT_EINVAL, "the exact DCT has integer output only with a quantiser step");
+        DctArgs d;
+        memset(&d, 0, sizeof(d));
+        const int wpf = setup_dct(&d, planes, n_planes, r, quant_step);
+        if (pitch_out_override > 0)
+            for (int p = 0; p < n_planes; ++p) d.pl[p].pitch_out = pitch_out_override;
+        if (int64_t(wpf) * n_frames >= (int64_t(1) << 31) / 4)
+            return fail(ADCT_EDIM, "stream too large for one launch");
+        d.in = frames;
+        d.out = recon;
+        d.coef_q = coef;
+        d.sse = reinterpret_cast<unsigned long long *>(sse);
+        d.fs_in = frame_stride;
+        d.fs_out = frame_stride_out;
+        d.n_frames = n_frames;
+        st = zero_u64(sse, int64_t(n_frames) * n_planes, hs);
+        if (st) return st;
+        return launch_dct(kEvaluate, d, wpf * n_frames, hs);
     }
     CodecArgs a;
     memset(&a, 0, sizeof(a));
@@ -309,6 +369,21 @@ adct_status adct_encode_blocks(const uint8_t *img, int H, int W, int pitch,
     if (st) return st;
     if ((coef_int && !aligned(coef_int, 4)) || (coef_scaled && !aligned(coef_scaled, 4)))
         return fail(ADCT_EDIM, "coefficient buffers must be 4-byte aligned");
+    if (t == ADCT_DCT) {
+        st = check_dct_args(r, quant_step);
+        if (st) return st;
+        if (coef_int && quant_step == 0)
+            return fail(ADCT_EINVAL, "the exact DCT has integer output only with a quantiser step");
+        DctArgs d;
+        memset(&d, 0, sizeof(d));
+        adct_plane pl = {0, H, W, pitch, 0};
+        const int waves = setup_dct(&d, &pl, 1, r, quant_step);
+        d.in = img;
+        d.coef_f = coef_scaled;
+        d.coef_q = coef_int;
+        d.n_frames = 1;
+        return launch_dct(kEncode, d, waves, reinterpret_cast<hipStream_t>(stream));
+    }
     CodecArgs a;
     memset(&a, 0, sizeof(a));
     Prepared pr;
@@ -331,9 +406,28 @@ adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled
     if (!out) return fail(ADCT_EINVAL, "out is null");
     if ((coef_int != nullptr) == (coef_scaled != nullptr))
         return fail(ADCT_EINVAL, "exactly one of coef_int / coef_scaled must be given");
-    if (coef_scaled) return fail(ADCT_ENOTSUP, "float coefficients decode through the exact-DCT path");
     adct_status st = check_plane(out, 0, H, W, pitch_out, "out");
     if (st) return st;
+    if (t == ADCT_DCT) {
+        st = check_dct_args(r, quant_step);
+        if (st) return st;
+        if (coef_int && quant_step == 0)
+            return fail(ADCT_EINVAL, "integer DCT coefficients are quantised levels: give quant_step");
+        if (coef_scaled && quant_step != 0)
+            return fail(ADCT_EINVAL, "float DCT coefficients are decoded without a quantiser step");
+        if (!aligned(coef_int ? (const void *)coef_int : (const void *)coef_scaled, 4))
+            return fail(ADCT_EDIM, "coefficients must be 4-byte aligned");
+        DctArgs d;
+        memset(&d, 0, sizeof(d));
+        adct_plane pl = {0, H, W, pitch_out, 0};
+        const int waves = setup_dct(&d, &pl, 1, r, quant_step);
+        d.out = out;
+        d.coef_f = const_cast<float *>(coef_scaled);
+        d.coef_q = const_cast<int16_t *>(coef_int);
+        d.n_frames = 1;
+        return launch_dct(kDecode, d, waves, reinterpret_cast<hipStream_t>(stream));
+    }
+    if (coef_scaled) return fail(ADCT_ENOTSUP, "float coefficients decode through the exact-DCT path");
     if (!aligned(coef_int, 4)) return fail(ADCT_EDIM, "coef_int must be 4-byte aligned");
     CodecArgs a;
     memset(&a, 0, sizeof(a));

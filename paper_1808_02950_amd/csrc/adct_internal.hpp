@@ -190,7 +190,29 @@ struct CodecArgs {
     double inv_step_d;   // 1 / step
 };
 
+struct DctArgs {
+    const uint8_t *in;
+    uint8_t *out;
+    float *coef_f;       // B (float32), [block][r]
+    int16_t *coef_q;     // quantised levels, [block][r] (step > 0)
+    unsigned long long *sse;
+    int64_t fs_in;
+    int64_t fs_out;
+    int32_t n_frames;
+    int32_t n_planes;
+    int32_t waves_per_frame;
+    int32_t blocks_per_frame;
+    int32_t r;
+    int32_t step;
+    float inv_step;
+    int32_t pad;
+    PlaneArg pl[kMaxPlanes];   // wave_start counts 16-block tiles
+    float C[64];               // orthonormal DCT-II, C[8k + x]
+};
+
 enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2 };
+
+adct_status launch_dct(Mode mode, const DctArgs &a, int total_waves, hipStream_t s);
 
 // Codec launch schedule: resident 4-wave workgroups per CU (0 = as many as
 // occupancy allows, -1 = one tile per wave, no persistence).

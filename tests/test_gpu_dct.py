@@ -1,0 +1,94 @@
+"""GPU parity of the exact-DCT comparator (FP32 on the matrix cores) against the
+float64 oracle.  Coefficients within 1e-5 of the block energy, PSNR within 1e-5
+relative; reconstructed pixels equal except where the exact value is within
+float32 noise of a half (those are counted and must be rare)."""
+
+import numpy as np
+import pytest
+
+import paper_1808_02950_amd as A
+from oracle import codec as Co
+from synth import ar1_image, video_base_planes, video_frame, video_spec
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, cuda):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(cuda)
+
+
+def _near_half(real, tol=1e-3):
+    return np.abs(real - np.floor(real) - 0.5) < tol
+
+
+def _check_recon(rec, ref, real):
+    diff = rec.astype(np.int64) != ref.astype(np.int64)
+    assert not np.any(diff & ~_near_half(real)), "pixel differs away from a half"
+    assert np.all(np.abs(rec.astype(np.int64) - ref.astype(np.int64)) <= 1)
+    return int(diff.sum())
+
+
+@pytest.mark.parametrize("r", [1, 10, 16, 17, 36, 64])
+def test_dct_zonal(cuda, r):
+    import torch
+    img = ar1_image(72, 136, 0.95, seed=r)
+    ref = Co.evaluate_dct(img, r)
+    d = _dev(img, cuda)
+    _, cf = A.encode_blocks(d, "DCT", r, want_int=False, want_scaled=True)
+    b = cf.cpu().numpy().astype(np.float64)
+    energy = np.sqrt(np.sum(Co.to_blocks(img).astype(np.float64) ** 2, axis=(1, 2)))
+    assert np.all(np.abs(b - ref["coef_scaled"]) <= 1e-5 * energy[:, None])
+    recon = torch.empty_like(d)
+    ev = A.evaluate_coding(d, "DCT", r, recon=recon)
+    _check_recon(recon.cpu().numpy(), ref["rec"], ref["real"])
+    if r == 64:
+        assert ev.sse == 0 == ref["sse"]
+    else:
+        assert abs(ev.psnr - ref["psnr"]) <= 1e-5 * ref["psnr"]
+    rec2 = A.decode_blocks(None, 72, 136, "DCT", r, coef_scaled=cf)
+    _check_recon(rec2.cpu().numpy(), ref["rec"], ref["real"])
+
+
+def test_dct_config1_512(cuda):
+    img = ar1_image(512, 512, 0.95, seed=0)
+    ref = Co.evaluate_dct(img, 10)
+    ev = A.evaluate_coding(_dev(img, cuda), "DCT", 10)
+    assert abs(ev.psnr - ref["psnr"]) <= 1e-5 * ref["psnr"]
+
+
+def test_dct_quantised(cuda):
+    import torch
+    img = ar1_image(64, 200, 0.95, seed=9)
+    ref = Co.evaluate_dct(img, 10, step=16)
+    d = _dev(img, cuda)
+    ci, cf = A.encode_blocks(d, "DCT", 10, 16, want_int=True, want_scaled=True)
+    q = ci.cpu().numpy().astype(np.int64)
+    x = ref["coef_scaled"] / 16
+    qref = (np.sign(x) * np.floor(np.abs(x) + 0.5)).astype(np.int64)
+    near = np.abs(np.abs(x) - np.floor(np.abs(x)) - 0.5) < 1e-4
+    assert not np.any((q != qref) & ~near)
+    recon = torch.empty_like(d)
+    ev = A.evaluate_coding(d, "DCT", 10, 16, recon=recon)
+    assert abs(ev.psnr - ref["psnr"]) <= 1e-5 * ref["psnr"]
+    rec2 = A.decode_blocks(ci, 64, 200, "DCT", 10, 16)
+    assert np.array_equal(rec2.cpu().numpy(), recon.cpu().numpy())
+
+
+def test_dct_stream(cuda):
+    spec = video_spec(n_frames=2, width=144, height=80, seed=3)
+    bases = video_base_planes(spec)
+    frames = np.stack([video_frame(spec, bases, f) for f in range(2)])
+    planes = [(o, h, w, w) for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets)]
+    sse = A.evaluate_stream(_dev(frames, cuda), planes, "DCT", 10, 16).cpu().numpy()
+    for f in range(2):
+        for p, ((h, w), o) in enumerate(zip(spec.plane_shapes, spec.plane_offsets)):
+            ref = Co.evaluate_dct(frames[f, o:o + h * w].reshape(h, w), 10, 16)
+            assert abs(int(sse[f, p]) - ref["sse"]) <= 1e-4 * ref["sse"] + 2
+
+
+def test_dct_argument_errors(cuda):
+    import torch
+    img = torch.zeros((16, 16), dtype=torch.uint8, device=cuda)
+    with pytest.raises(A.AdctError):
+        A.encode_blocks(img, "DCT", 10, 0, want_int=True)      # integer output needs a step
