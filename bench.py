@@ -82,6 +82,32 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def other_rows():
+    """Timings of the other hot-path rows on the same GPU (each synchronised)."""
+    import paper_1808_02950_amd as A
+
+    res = {}
+    p2 = [0, 1, -1, 2, -2]
+    p4 = [0, 1, -1, 2, -2, 3, -3, 4, -4]
+    A.derive_transform(p2, A.SEARCH_CLOSURE)                     # warm
+    t0 = time.perf_counter()
+    mats, _, leaves, dead = A.derive_transform(p2, A.SEARCH_CLOSURE)
+    res["search_closure_P2_720_orders"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
+                                           "matrices": int(len(mats)), "leaves": leaves,
+                                           "dead_paths": dead}
+    A.search_topk(p4, 64)
+    t0 = time.perf_counter()
+    vec, idx, cos = A.search_topk(p4, 64)
+    t_scan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, n64 = A.orthogonal_tuples([vec[r] for r in range(8)])
+    t_tup = time.perf_counter() - t0
+    res["search_topk_9pow8_k64"] = {"ms": round(t_scan * 1e3, 2), "candidates": 9 ** 8 - 1,
+                                    "rows": 8, "Gcand_rows_per_s": round(8 * (9 ** 8 - 1) / t_scan / 1e9, 2),
+                                    "tuples_ms": round(t_tup * 1e3, 2), "orthogonal_tuples": n64}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +236,7 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
                      "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
     }
+    out["other_rows"] = other_rows()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_frames, spec.n_frames), r, step)

@@ -175,6 +175,60 @@ adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, in
                                  int16_t *coef, uint8_t *recon, int64_t frame_stride_out,
                                  uint64_t *sse, adct_stream_t stream);
 
+/* ---------------------------------------------------------------- search */
+
+/* Search modes of adct_derive_transform (Sec. 3.5 and 4.1).  Exact ties in
+ * angle are real (scalar multiples, mirror images, equal irrational angles):
+ *   CLOSURE    every matrix reachable under any resolution of the exact ties
+ *              (cosines within 1e-12 are tied; groups by single linkage)
+ *   CANONICAL  one matrix per order: among tied candidates the smaller
+ *              squared norm, then the smaller canonical index */
+typedef enum { ADCT_SEARCH_CLOSURE = 0, ADCT_SEARCH_CANONICAL = 1 } adct_search_mode;
+
+/* Greedy angle-similarity search (Eq. (6), the algorithm of Sec. 3.5): for each
+ * row order, each row k in turn takes the candidate of D = P^8 \ {0} with the
+ * smallest angle to DCT row k among those orthogonal to every row chosen so
+ * far; an order whose feasible set empties is dead.
+ *   P, nP         host: the entry set (distinct values in [-4, 4], must hold 0),
+ *                 1 <= nP <= 9.  The canonical index of a vector is its
+ *                 odometer rank over P ordered 0, 1, -1, 2, -2, ... (first
+ *                 coordinate most significant).
+ *   orders        host: n_orders x n_free row indices (0-based) of the free
+ *                 rows, or NULL for all orders of the free rows
+ *   fix_rows_1_5  nonzero: rows 1 and 5 (indices 0 and 4) are fixed to
+ *                 [1]*8 and [1,-1,-1,1,1,-1,-1,1] (Sec. 4.1) and the other six
+ *                 rows are free (720 orders); zero: all 8 rows free
+ *   out, cap_out  host: the distinct matrices found, sorted by their 64 bytes
+ *   n_out         host: number of distinct matrices (also when > cap_out,
+ *                 which returns ADCT_ECAP after filling cap_out)
+ *   angles_out    host, nullable: cap_out x 8 angles (radians) of each row to
+ *                 the matching DCT row
+ *   leaves_out, dead_out  host, nullable: completed and dead (order, tie
+ *                 branch) paths
+ * Synchronises `stream`; allocates and frees its own device scratch. */
+adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8_t *orders,
+                                  int n_orders, int fix_rows_1_5, adct_matrix *out, int cap_out,
+                                  int *n_out, double *angles_out, int64_t *leaves_out,
+                                  int64_t *dead_out, adct_stream_t stream);
+
+/* Top-k form of the row search (Sec. 3.3 objective over the whole space, one
+ * list per DCT row): for each row r the k candidates of P^8 \ {0} with the
+ * smallest angle, ranked by cosine tie groups (1e-12), then squared norm, then
+ * canonical index.  primitive != 0 keeps only vectors whose entries have gcd 1
+ * (a positive multiple of a row gives the same normalised row).
+ *   vec_out  host int8 [8][k][8];  idx_out host [8][k] canonical indices;
+ *   cos_out  host [8][k].  Synchronises `stream`. */
+adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8_t *vec_out,
+                             int64_t *idx_out, double *cos_out, adct_stream_t stream);
+
+/* Every choice of one vector per row list whose 8 vectors are pairwise
+ * orthogonal (T T^T diagonal, Sec. 3.4), in lexicographic order of positions.
+ *   lists  host int8: the 8 lists concatenated, list r has len[r] vectors of 8
+ *   out    host int32 [cap][8] positions;  n_total  host: number of tuples (all
+ *          of them, even beyond cap).  Synchronises `stream`. */
+adct_status adct_orthogonal_tuples(const int8_t *lists, const int *len, int32_t *out, int64_t cap,
+                                   int64_t *n_total, adct_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

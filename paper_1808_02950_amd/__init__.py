@@ -64,6 +64,11 @@ _SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_double), _P]),
     "adct_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I,
                                   ctypes.POINTER(Matrix), _I, _I, _P, _P, _I64, _P, _P]),
+    "adct_derive_transform": (_I, [_P, _I, _I, _P, _I, _I, ctypes.POINTER(Matrix), _I,
+                                   ctypes.POINTER(_I), _P, ctypes.POINTER(_I64),
+                                   ctypes.POINTER(_I64), _P]),
+    "adct_search_topk": (_I, [_P, _I, _I, _I, _P, _P, _P, _P]),
+    "adct_orthogonal_tuples": (_I, [_P, ctypes.POINTER(_I), _P, _I64, ctypes.POINTER(_I64), _P]),
 }
 
 
@@ -237,3 +242,54 @@ def psnr_from_sse(sse: int, npix: int) -> float:
     if sse == 0:
         return math.inf
     return 10.0 * math.log10(255.0 * 255.0 * npix / sse)
+
+
+# ---------------------------------------------------------------- search
+
+SEARCH_CLOSURE, SEARCH_CANONICAL = 0, 1
+
+
+def derive_transform(P, mode: int = SEARCH_CLOSURE, orders=None, fix_rows_1_5: bool = True,
+                     cap: int = 4096, stream=None):
+    """adct_derive_transform.  Returns (matrices (n, 8, 8) int64, angles (n, 8)
+    radians, leaves, dead)."""
+    p = np.ascontiguousarray(np.asarray(P, dtype=np.int8))
+    if orders is not None:
+        o = np.ascontiguousarray(np.asarray(orders, dtype=np.uint8))
+        optr, n_orders = o.ctypes.data, o.shape[0]
+    else:
+        o, optr, n_orders = None, None, 0
+    out = (Matrix * cap)()
+    ang = np.zeros((cap, 8), dtype=np.float64)
+    n, leaves, dead = _I(), _I64(), _I64()
+    _check(lib().adct_derive_transform(p.ctypes.data, len(p), mode, optr, n_orders,
+                                       1 if fix_rows_1_5 else 0, out, cap, ctypes.byref(n),
+                                       ang.ctypes.data, ctypes.byref(leaves), ctypes.byref(dead),
+                                       _stream(stream)))
+    mats = np.array([np.array(list(out[i].T), dtype=np.int64).reshape(8, 8)
+                     for i in range(n.value)]).reshape(-1, 8, 8)
+    return mats, ang[:n.value], leaves.value, dead.value
+
+
+def search_topk(P, k: int, primitive: bool = True, stream=None):
+    """adct_search_topk.  Returns (vec (8, k, 8) int8, idx (8, k), cos (8, k))."""
+    p = np.ascontiguousarray(np.asarray(P, dtype=np.int8))
+    vec = np.zeros((8, k, 8), dtype=np.int8)
+    idx = np.zeros((8, k), dtype=np.int64)
+    cos = np.zeros((8, k), dtype=np.float64)
+    _check(lib().adct_search_topk(p.ctypes.data, len(p), k, 1 if primitive else 0, vec.ctypes.data,
+                                  idx.ctypes.data, cos.ctypes.data, _stream(stream)))
+    return vec, idx, cos
+
+
+def orthogonal_tuples(lists, cap: int = 1 << 20, stream=None):
+    """adct_orthogonal_tuples.  lists: 8 arrays (len_r, 8).  Returns
+    (tuples (min(n, cap), 8) int32, n)."""
+    arrs = [np.asarray(l, dtype=np.int8).reshape(-1, 8) for l in lists]
+    flat = np.ascontiguousarray(np.concatenate(arrs, axis=0))
+    lens = (_I * 8)(*[a.shape[0] for a in arrs])
+    out = np.zeros((max(cap, 1), 8), dtype=np.int32)
+    n = _I64()
+    _check(lib().adct_orthogonal_tuples(flat.ctypes.data, lens, out.ctypes.data, cap,
+                                        ctypes.byref(n), _stream(stream)))
+    return out[:min(n.value, cap)], n.value

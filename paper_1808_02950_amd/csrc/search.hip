@@ -1,0 +1,748 @@
+// Angle-similarity search for low-complexity DCT rows (Sec. 3 and Sec. 4.1 of
+// the paper), batched on the GPU.
+//
+// The search space D = P^8 (Sec. 3.2) is enumerated once into a device table
+// (packed int8 vectors, squared norms, cosines to the eight DCT rows).  The
+// greedy problem of Eq. (6) is then answered query by query: a query is (rows
+// already chosen, DCT row to approximate); the device finds the largest cosine
+// (smallest angle, Sec. 3.3) among candidates orthogonal to every chosen row
+// (Sec. 3.4) and collects every candidate within a small window of it; the host
+// groups exact ties and expands the search tree level by level, so each launch
+// answers every open query of one depth.
+//
+// The top-k form scans the whole space once per row with a per-workgroup LDS
+// histogram of the angle, picks a cosine threshold per row, collects the
+// candidates above it and ranks them on the host.  Orthogonal 8-tuples of the
+// ranked lists are found by a depth-first search over orthogonality bitsets the
+// device computes.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "adct_internal.hpp"
+
+namespace adct {
+namespace {
+
+constexpr double kTieEps = 1e-12;     // cosines this close are an exact tie in reals
+constexpr double kWindow = 1e-6;      // collection window below the best cosine
+constexpr int kMaxChosen = 7;
+constexpr int kHistBins = 448;        // 8 bins per octave of 1 - cos, 56 octaves
+
+struct DctRows {
+    double c[64];                     // orthonormal DCT-II rows, c[8k + n]
+};
+
+struct Digits {
+    int8_t d[12];
+};
+
+DctRows dct_rows() {
+    DctRows r;
+    for (int k = 0; k < 8; ++k)
+        for (int x = 0; x < 8; ++x)
+            r.c[8 * k + x] = (k == 0 ? sqrt(0.125) : 0.5) * cos((2 * x + 1) * k * M_PI / 16.0);
+    return r;
+}
+
+__device__ __forceinline__ int sdot8(uint2 a, uint2 b) {
+    return __builtin_amdgcn_sdot4(int(a.x), int(b.x), __builtin_amdgcn_sdot4(int(a.y), int(b.y), 0, false),
+                                  false);
+}
+
+// monotone map of a double onto uint64 (for atomicMax)
+__device__ __forceinline__ unsigned long long order_key(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double key_value(unsigned long long k) {
+    const unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __builtin_bit_cast(double, u);
+}
+
+// ------------------------------------------------------------ enumeration
+
+__global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, int *norm2, double *cosv,
+                       uint8_t *prim, DctRows rows) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t idx = i + 1;                             // canonical index; 0 is the zero vector
+    int v[8];
+    for (int e = 7; e >= 0; --e) {                   // first coordinate most significant
+        v[e] = dg.d[idx % b];
+        idx /= b;
+    }
+    uint32_t lo = 0, hi = 0;
+    int s = 0;
+    bool odd = false, non3 = false;
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t byte = uint32_t(uint8_t(int8_t(v[e])));
+        if (e < 4) lo |= byte << (8 * e); else hi |= byte << (8 * (e - 4));
+        s += v[e] * v[e];
+        odd |= (v[e] & 1) != 0;
+        non3 |= (v[e] % 3) != 0;
+    }
+    vec[i] = make_uint2(lo, hi);
+    norm2[i] = s;
+    // gcd of the entries is 1 exactly when some entry is odd and some entry is
+    // not a multiple of 3 (entries are within +-4)
+    prim[i] = uint8_t(odd && non3);
+    const double inv = 1.0 / sqrt(double(s));
+    for (int r = 0; r < 8; ++r) {
+        double dot = 0.0;
+        for (int e = 0; e < 8; ++e) dot = fma(double(v[e]), rows.c[8 * r + e], dot);
+        cosv[i * 8 + r] = dot * inv;
+    }
+}
+
+// ------------------------------------------------------------ greedy queries
+
+struct Query {
+    uint2 chosen[kMaxChosen];
+    int nchosen;
+    int row;
+};
+
+__device__ __forceinline__ bool feasible(const Query &q, uint2 v) {
+    bool ok = true;
+    for (int j = 0; j < q.nchosen; ++j) ok &= sdot8(v, q.chosen[j]) == 0;
+    return ok;
+}
+
+__global__ __launch_bounds__(256) void k_qmax(const Query *qs, int64_t n, const uint2 *vec,
+                                             const double *cosv, unsigned long long *best) {
+    const Query q = qs[blockIdx.y];
+    double m = -2.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        if (feasible(q, vec[i])) m = fmax(m, cosv[i * 8 + q.row]);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m > -2.0) atomicMax(best + blockIdx.y, order_key(m));
+}
+
+__global__ __launch_bounds__(256) void k_qcollect(const Query *qs, int64_t n, const uint2 *vec,
+                                                 const double *cosv, const unsigned long long *best,
+                                                 int cap, int64_t *out_idx, double *out_cos,
+                                                 int *count) {
+    const int qi = blockIdx.y;
+    if (best[qi] == 0) return;                                  // no feasible candidate
+    const Query q = qs[qi];
+    const double lo = key_value(best[qi]) - kWindow;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const double c = cosv[i * 8 + q.row];
+        if (c >= lo && feasible(q, vec[i])) {
+            const int pos = atomicAdd(count + qi, 1);
+            if (pos < cap) {
+                out_idx[int64_t(qi) * cap + pos] = i;
+                out_cos[int64_t(qi) * cap + pos] = c;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ top-k scan
+
+__device__ __forceinline__ int angle_bin(double c) {
+    const double u = 1.0 - c;                                   // >= 0 up to rounding
+    if (!(u > 0.0)) return kHistBins - 1;
+    const int b = int(-log2(u) * 8.0);
+    return b < 0 ? -1 : (b >= kHistBins ? kHistBins - 1 : b);
+}
+
+__global__ __launch_bounds__(256) void k_hist(int64_t n, const double *cosv, const uint8_t *prim,
+                                             int primitive, unsigned *hist) {
+    __shared__ unsigned h[8 * kHistBins];
+    for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        if (primitive && !prim[i]) continue;
+        for (int r = 0; r < 8; ++r) {
+            const int bn = angle_bin(cosv[i * 8 + r]);
+            if (bn >= 0) atomicAdd(&h[r * kHistBins + bn], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x)
+        if (h[i]) atomicAdd(hist + i, h[i]);
+}
+
+struct Thresholds {
+    int bin[8];                                                 // collect bins >= bin[r]
+    int64_t cap[8];
+    int64_t off[8];
+};
+
+__global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const double *cosv, const uint8_t *prim,
+                                                     int primitive, Thresholds th, int64_t *out_idx,
+                                                     double *out_cos, unsigned long long *count) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        if (primitive && !prim[i]) continue;
+        for (int r = 0; r < 8; ++r) {
+            const double c = cosv[i * 8 + r];
+            if (angle_bin(c) >= th.bin[r]) {
+                const unsigned long long pos = atomicAdd(count + r, 1ull);
+                if (int64_t(pos) < th.cap[r]) {
+                    out_idx[th.off[r] + int64_t(pos)] = i;
+                    out_cos[th.off[r] + int64_t(pos)] = c;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ orthogonality bitsets
+
+// bits[(pair * kmax + a) * words + w] bit j: lists[r1][a] . lists[r2][64 w + j] == 0
+__global__ void k_ortho_bits(const uint2 *lists, const int *len, const int *base, int kmax, int words,
+                             unsigned long long *bits) {
+    const int pair = blockIdx.y;
+    int r1 = 0, rem = pair;
+    while (rem >= 7 - r1) {
+        rem -= 7 - r1;
+        ++r1;
+    }
+    const int r2 = r1 + 1 + rem;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int a = int(t / words), w = int(t % words);
+    if (a >= len[r1]) return;
+    const uint2 va = lists[base[r1] + a];
+    unsigned long long word = 0;
+    for (int j = 0; j < 64; ++j) {
+        const int q = 64 * w + j;
+        if (q < len[r2] && sdot8(va, lists[base[r2] + q]) == 0) word |= 1ull << j;
+    }
+    bits[(int64_t(pair) * kmax + a) * words + w] = word;
+}
+
+// ------------------------------------------------------------ host helpers
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+template <class T>
+adct_status dalloc(DevBuf &b, size_t count) {
+    ADCT_HIP(hipMalloc(&b.p, std::max<size_t>(count, 1) * sizeof(T)));
+    return ADCT_OK;
+}
+
+struct Space {
+    int b = 0;
+    int8_t digits[9] = {};
+    int64_t n = 0;
+    DevBuf vec, norm2, cosv, prim;
+};
+
+adct_status canonical_digits(const int8_t *P, int nP, int8_t *out, int *b) {
+    if (!P) return fail(ADCT_EINVAL, "P is null");
+    if (nP < 1 || nP > 9) return fail(ADCT_ERANGE, "|P| must be in [1, 9]");
+    std::vector<int> v(P, P + nP);
+    std::sort(v.begin(), v.end());
+    if (std::unique(v.begin(), v.end()) != v.end()) return fail(ADCT_EINVAL, "P has repeated entries");
+    for (int x : v)
+        if (x < -4 || x > 4) return fail(ADCT_ERANGE, "entries of P must be within [-4, 4]");
+    // order 0, 1, -1, 2, -2, ... (the canonical index's digit order)
+    std::sort(v.begin(), v.end(), [](int a, int c) {
+        const int aa = a < 0 ? -a : a, cc = c < 0 ? -c : c;
+        return aa != cc ? aa < cc : (a > c);
+    });
+    if (v[0] != 0) return fail(ADCT_EINVAL, "P must contain 0");
+    for (int i = 0; i < nP; ++i) out[i] = int8_t(v[i]);
+    *b = nP;
+    return ADCT_OK;
+}
+
+adct_status build_space(const int8_t *P, int nP, Space &sp, hipStream_t s) {
+    adct_status st = canonical_digits(P, nP, sp.digits, &sp.b);
+    if (st) return st;
+    int64_t total = 1;
+    for (int i = 0; i < 8; ++i) total *= sp.b;
+    sp.n = total - 1;
+    if (sp.n < 1) return fail(ADCT_ERANGE, "search space is empty");
+    if ((st = dalloc<uint2>(sp.vec, sp.n))) return st;
+    if ((st = dalloc<int>(sp.norm2, sp.n))) return st;
+    if ((st = dalloc<double>(sp.cosv, sp.n * 8))) return st;
+    if ((st = dalloc<uint8_t>(sp.prim, sp.n))) return st;
+    Digits dg;
+    memset(&dg, 0, sizeof(dg));
+    for (int i = 0; i < sp.b; ++i) dg.d[i] = sp.digits[i];
+    const int64_t blocks = (sp.n + 255) / 256;
+    hipLaunchKernelGGL(k_enum, dim3(unsigned(blocks)), dim3(256), 0, s, sp.b, dg, sp.n,
+                       (uint2 *)sp.vec.p, (int *)sp.norm2.p, (double *)sp.cosv.p, (uint8_t *)sp.prim.p,
+                       dct_rows());
+    ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
+}
+
+// vector of canonical index idx (>= 1) as 8 int8 entries
+void decode_index(const Space &sp, int64_t idx, int8_t *v) {
+    for (int e = 7; e >= 0; --e) {
+        v[e] = sp.digits[idx % sp.b];
+        idx /= sp.b;
+    }
+}
+
+uint2 pack8(const int8_t *v) {
+    uint32_t lo = 0, hi = 0;
+    for (int e = 0; e < 4; ++e) lo |= uint32_t(uint8_t(v[e])) << (8 * e);
+    for (int e = 0; e < 4; ++e) hi |= uint32_t(uint8_t(v[4 + e])) << (8 * e);
+    return make_uint2(lo, hi);
+}
+
+int norm2_of(const int8_t *v) {
+    int s = 0;
+    for (int e = 0; e < 8; ++e) s += v[e] * v[e];
+    return s;
+}
+
+struct Cand {
+    int64_t idx;    // canonical index
+    double cos;
+    int norm2;
+};
+
+// best tie group of a collected window: sort by cosine (descending, then index),
+// extend from the top while consecutive cosines differ by at most kTieEps
+std::vector<Cand> top_group(std::vector<Cand> c) {
+    std::sort(c.begin(), c.end(), [](const Cand &a, const Cand &b) {
+        return a.cos != b.cos ? a.cos > b.cos : a.idx < b.idx;
+    });
+    size_t k = c.empty() ? 0 : 1;
+    while (k < c.size() && c[k - 1].cos - c[k].cos <= kTieEps) ++k;
+    c.resize(k);
+    return c;
+}
+
+// canonical rank: tie groups of cosine (single linkage on the sorted values),
+// then smaller squared norm, then smaller index
+void canonical_sort(std::vector<Cand> &c) {
+    std::sort(c.begin(), c.end(), [](const Cand &a, const Cand &b) {
+        return a.cos != b.cos ? a.cos > b.cos : a.idx < b.idx;
+    });
+    std::vector<int> grp(c.size(), 0);
+    for (size_t i = 1; i < c.size(); ++i) grp[i] = grp[i - 1] + (c[i - 1].cos - c[i].cos > kTieEps ? 1 : 0);
+    std::vector<size_t> ord(c.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+        if (grp[a] != grp[b]) return grp[a] < grp[b];
+        if (c[a].norm2 != c[b].norm2) return c[a].norm2 < c[b].norm2;
+        return c[a].idx < c[b].idx;
+    });
+    std::vector<Cand> out;
+    out.reserve(c.size());
+    for (size_t i : ord) out.push_back(c[i]);
+    c.swap(out);
+}
+
+// prefix tree of row orders
+struct Tree {
+    std::vector<std::map<int, int>> kids;
+    std::vector<int64_t> leaves;          // orders ending under each node
+    int add_node() {
+        kids.emplace_back();
+        leaves.push_back(0);
+        return int(kids.size()) - 1;
+    }
+};
+
+struct State {
+    int node;
+    int8_t rows[8][8];
+    bool set[8];
+};
+
+struct MatKey {
+    std::array<uint8_t, 64> b;
+    bool operator<(const MatKey &o) const { return memcmp(b.data(), o.b.data(), 64) < 0; }
+};
+
+// Answer a batch of queries: per query the collected window (or none when the
+// feasible set is empty).
+adct_status run_queries(const Space &sp, const std::vector<Query> &qs,
+                        std::vector<std::vector<Cand>> &res, std::vector<char> &dead, hipStream_t s) {
+    const int nq = int(qs.size());
+    res.assign(nq, {});
+    dead.assign(nq, 0);
+    if (nq == 0) return ADCT_OK;
+    int cap = 64;
+    DevBuf dq, dbest, dcount;
+    adct_status st;
+    if ((st = dalloc<Query>(dq, nq))) return st;
+    if ((st = dalloc<unsigned long long>(dbest, nq))) return st;
+    if ((st = dalloc<int>(dcount, nq))) return st;
+    ADCT_HIP(hipMemcpyAsync(dq.p, qs.data(), sizeof(Query) * nq, hipMemcpyHostToDevice, s));
+    ADCT_HIP(hipMemsetAsync(dbest.p, 0, sizeof(unsigned long long) * nq, s));
+    const unsigned chunks = unsigned(std::min<int64_t>((sp.n + 255) / 256, 64));
+    for (int y0 = 0; y0 < nq; y0 += 65535) {
+        const int ny = std::min(nq - y0, 65535);
+        hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, sp.n,
+                           (const uint2 *)sp.vec.p, (const double *)sp.cosv.p,
+                           (unsigned long long *)dbest.p + y0);
+        ADCT_HIP(hipGetLastError());
+    }
+    for (;;) {
+        DevBuf didx, dcos;
+        if ((st = dalloc<int64_t>(didx, int64_t(nq) * cap))) return st;
+        if ((st = dalloc<double>(dcos, int64_t(nq) * cap))) return st;
+        ADCT_HIP(hipMemsetAsync(dcount.p, 0, sizeof(int) * nq, s));
+        for (int y0 = 0; y0 < nq; y0 += 65535) {
+            const int ny = std::min(nq - y0, 65535);
+            hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0,
+                               sp.n, (const uint2 *)sp.vec.p, (const double *)sp.cosv.p,
+                               (const unsigned long long *)dbest.p + y0, cap,
+                               (int64_t *)didx.p + int64_t(y0) * cap, (double *)dcos.p + int64_t(y0) * cap,
+                               (int *)dcount.p + y0);
+            ADCT_HIP(hipGetLastError());
+        }
+        std::vector<int> cnt(nq);
+        std::vector<unsigned long long> best(nq);
+        ADCT_HIP(hipMemcpyAsync(cnt.data(), dcount.p, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(best.data(), dbest.p, sizeof(unsigned long long) * nq, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipStreamSynchronize(s));
+        const int need = *std::max_element(cnt.begin(), cnt.end());
+        if (need > cap) {                    // window larger than the buffer: grow and redo
+            cap = need;
+            continue;
+        }
+        std::vector<int64_t> idx(int64_t(nq) * cap);
+        std::vector<double> cs(int64_t(nq) * cap);
+        ADCT_HIP(hipMemcpyAsync(idx.data(), didx.p, sizeof(int64_t) * idx.size(), hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(cs.data(), dcos.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < nq; ++q) {
+            if (best[q] == 0) {
+                dead[q] = 1;
+                continue;
+            }
+            for (int j = 0; j < cnt[q]; ++j) {
+                Cand c;
+                c.idx = idx[int64_t(q) * cap + j] + 1;
+                c.cos = cs[int64_t(q) * cap + j];
+                int8_t v[8];
+                decode_index(sp, c.idx, v);
+                c.norm2 = norm2_of(v);
+                res[q].push_back(c);
+            }
+        }
+        return ADCT_OK;
+    }
+}
+
+void fill_matrix(const int8_t (*rows)[8], adct_matrix *m) {
+    for (int k = 0; k < 8; ++k) {
+        int32_t s = 0;
+        for (int e = 0; e < 8; ++e) {
+            m->T[8 * k + e] = rows[k][e];
+            s += rows[k][e] * rows[k][e];
+        }
+        m->n[k] = s;
+    }
+}
+
+void row_angles(const adct_matrix &m, double *out) {
+    const DctRows r = dct_rows();
+    for (int k = 0; k < 8; ++k) {
+        double dot = 0.0;
+        for (int e = 0; e < 8; ++e) dot += m.T[8 * k + e] * r.c[8 * k + e];
+        const double c = dot / sqrt(double(m.n[k]));
+        out[k] = acos(std::max(-1.0, std::min(1.0, c)));
+    }
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+extern "C" {
+
+adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8_t *orders,
+                                  int n_orders, int fix_rows_1_5, adct_matrix *out, int cap_out,
+                                  int *n_out, double *angles_out, int64_t *leaves_out,
+                                  int64_t *dead_out, adct_stream_t stream) {
+    if (mode != ADCT_SEARCH_CLOSURE && mode != ADCT_SEARCH_CANONICAL)
+        return fail(ADCT_EINVAL, "mode must be ADCT_SEARCH_CLOSURE or ADCT_SEARCH_CANONICAL");
+    if (!n_out) return fail(ADCT_EINVAL, "n_out is null");
+    if (cap_out < 0 || (cap_out > 0 && !out)) return fail(ADCT_EINVAL, "out is null");
+    std::vector<int> free_rows;
+    for (int k = 0; k < 8; ++k)
+        if (!fix_rows_1_5 || (k != 0 && k != 4)) free_rows.push_back(k);
+    const int nf = int(free_rows.size());
+    // the order list: given, or every permutation of the free rows
+    std::vector<std::vector<int>> ords;
+    if (orders) {
+        if (n_orders < 1) return fail(ADCT_ERANGE, "n_orders must be >= 1");
+        for (int o = 0; o < n_orders; ++o) {
+            std::vector<int> ord(orders + int64_t(o) * nf, orders + int64_t(o + 1) * nf);
+            std::vector<int> srt = ord;
+            std::sort(srt.begin(), srt.end());
+            if (srt != free_rows) return fail(ADCT_EINVAL, "each order must be a permutation of the free rows");
+            ords.push_back(ord);
+        }
+    } else {
+        std::vector<int> ord = free_rows;
+        do ords.push_back(ord);
+        while (std::next_permutation(ord.begin(), ord.end()));
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Space sp;
+    adct_status st = build_space(P, nP, sp, s);
+    if (st) return st;
+
+    Tree tr;
+    tr.add_node();
+    for (const auto &ord : ords) {
+        int node = 0;
+        tr.leaves[0]++;
+        for (int k : ord) {
+            auto it = tr.kids[node].find(k);
+            int nx;
+            if (it == tr.kids[node].end()) {
+                nx = tr.add_node();
+                tr.kids[node][k] = nx;
+            } else {
+                nx = it->second;
+            }
+            node = nx;
+            tr.leaves[node]++;
+        }
+    }
+
+    State root;
+    memset(&root, 0, sizeof(root));
+    root.node = 0;
+    if (fix_rows_1_5) {
+        const int8_t r0[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+        const int8_t r4[8] = {1, -1, -1, 1, 1, -1, -1, 1};
+        memcpy(root.rows[0], r0, 8);
+        memcpy(root.rows[4], r4, 8);
+        root.set[0] = root.set[4] = true;
+    }
+    std::map<MatKey, adct_matrix> found;
+    int64_t leaves = 0, dead = 0;
+    std::vector<State> frontier{root};
+    while (!frontier.empty()) {
+        std::vector<Query> qs;
+        std::vector<std::pair<int, int>> qmeta;          // (state, row)
+        for (size_t si = 0; si < frontier.size(); ++si) {
+            const State &S = frontier[si];
+            for (const auto &kv : tr.kids[S.node]) {
+                Query q;
+                memset(&q, 0, sizeof(q));
+                for (int k = 0; k < 8; ++k)
+                    if (S.set[k]) q.chosen[q.nchosen++] = pack8(S.rows[k]);
+                q.row = kv.first;
+                qs.push_back(q);
+                qmeta.emplace_back(int(si), kv.first);
+            }
+        }
+        std::vector<std::vector<Cand>> res;
+        std::vector<char> isdead;
+        if ((st = run_queries(sp, qs, res, isdead, s))) return st;
+        std::vector<State> next;
+        for (size_t q = 0; q < qs.size(); ++q) {
+            const State &S = frontier[qmeta[q].first];
+            const int row = qmeta[q].second;
+            const int child = tr.kids[S.node].at(row);
+            if (isdead[q]) {
+                dead += tr.leaves[child];
+                continue;
+            }
+            std::vector<Cand> grp = top_group(res[q]);
+            if (mode == ADCT_SEARCH_CANONICAL) {
+                canonical_sort(grp);
+                grp.resize(1);
+            }
+            for (const Cand &c : grp) {
+                State N = S;
+                N.node = child;
+                decode_index(sp, c.idx, N.rows[row]);
+                N.set[row] = true;
+                if (tr.kids[child].empty()) {
+                    adct_matrix m;
+                    fill_matrix(N.rows, &m);
+                    MatKey key;
+                    memcpy(key.b.data(), m.T, 64);
+                    found[key] = m;
+                    leaves++;
+                } else {
+                    next.push_back(N);
+                }
+            }
+        }
+        frontier.swap(next);
+    }
+    *n_out = int(found.size());
+    if (leaves_out) *leaves_out = leaves;
+    if (dead_out) *dead_out = dead;
+    int i = 0;
+    for (const auto &kv : found) {
+        if (i >= cap_out) break;
+        out[i] = kv.second;
+        if (angles_out) row_angles(kv.second, angles_out + 8 * i);
+        ++i;
+    }
+    if (int(found.size()) > cap_out) return fail(ADCT_ECAP, "output capacity too small");
+    return ADCT_OK;
+}
+
+adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8_t *vec_out,
+                             int64_t *idx_out, double *cos_out, adct_stream_t stream) {
+    if (k < 1) return fail(ADCT_ERANGE, "k must be >= 1");
+    if (!vec_out || !idx_out || !cos_out) return fail(ADCT_EINVAL, "outputs are required");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Space sp;
+    adct_status st = build_space(P, nP, sp, s);
+    if (st) return st;
+    DevBuf dhist;
+    if ((st = dalloc<unsigned>(dhist, 8 * kHistBins))) return st;
+    ADCT_HIP(hipMemsetAsync(dhist.p, 0, sizeof(unsigned) * 8 * kHistBins, s));
+    const unsigned grid = unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), 0, s, sp.n, (const double *)sp.cosv.p,
+                       (const uint8_t *)sp.prim.p, primitive, (unsigned *)dhist.p);
+    ADCT_HIP(hipGetLastError());
+    std::vector<unsigned> hist(8 * kHistBins);
+    ADCT_HIP(hipMemcpyAsync(hist.data(), dhist.p, sizeof(unsigned) * hist.size(), hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipStreamSynchronize(s));
+    // per row the highest bin whose cumulative count (from the smallest angle)
+    // reaches k + a margin, so the tie group at position k lies inside
+    Thresholds th;
+    int64_t total = 0;
+    for (int r = 0; r < 8; ++r) {
+        int64_t cum = 0;
+        int bn = kHistBins - 1;
+        for (; bn >= 0; --bn) {
+            cum += hist[r * kHistBins + bn];
+            if (cum >= int64_t(k) + 64) break;
+        }
+        if (bn < 0) bn = 0;
+        th.bin[r] = bn;
+        th.cap[r] = cum;
+        th.off[r] = total;
+        total += cum;
+    }
+    DevBuf didx, dcos, dcnt;
+    if ((st = dalloc<int64_t>(didx, total))) return st;
+    if ((st = dalloc<double>(dcos, total))) return st;
+    if ((st = dalloc<unsigned long long>(dcnt, 8))) return st;
+    ADCT_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(unsigned long long) * 8, s));
+    hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const double *)sp.cosv.p,
+                       (const uint8_t *)sp.prim.p, primitive, th, (int64_t *)didx.p, (double *)dcos.p,
+                       (unsigned long long *)dcnt.p);
+    ADCT_HIP(hipGetLastError());
+    std::vector<int64_t> idx(std::max<int64_t>(total, 1));
+    std::vector<double> cs(std::max<int64_t>(total, 1));
+    std::vector<unsigned long long> cnt(8);
+    ADCT_HIP(hipMemcpyAsync(idx.data(), didx.p, sizeof(int64_t) * total, hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipMemcpyAsync(cs.data(), dcos.p, sizeof(double) * total, hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipMemcpyAsync(cnt.data(), dcnt.p, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < 8; ++r) {
+        if (int64_t(cnt[r]) != th.cap[r]) return fail(ADCT_EDEVICE, "top-k collection count mismatch");
+        std::vector<Cand> c(size_t(th.cap[r]));
+        for (int64_t j = 0; j < th.cap[r]; ++j) {
+            c[j].idx = idx[th.off[r] + j] + 1;
+            c[j].cos = cs[th.off[r] + j];
+            int8_t v[8];
+            decode_index(sp, c[j].idx, v);
+            c[j].norm2 = norm2_of(v);
+        }
+        canonical_sort(c);
+        if (int64_t(c.size()) < k) return fail(ADCT_ERANGE, "fewer candidates than k");
+        for (int j = 0; j < k; ++j) {
+            decode_index(sp, c[j].idx, vec_out + (int64_t(r) * k + j) * 8);
+            idx_out[int64_t(r) * k + j] = c[j].idx;
+            cos_out[int64_t(r) * k + j] = c[j].cos;
+        }
+    }
+    return ADCT_OK;
+}
+
+adct_status adct_orthogonal_tuples(const int8_t *lists, const int *len, int32_t *out, int64_t cap,
+                                   int64_t *n_total, adct_stream_t stream) {
+    if (!lists || !len || !n_total) return fail(ADCT_EINVAL, "lists, len and n_total are required");
+    if (cap < 0 || (cap > 0 && !out)) return fail(ADCT_EINVAL, "out is null");
+    int kmax = 0, base[8], tot = 0;
+    for (int r = 0; r < 8; ++r) {
+        if (len[r] < 0) return fail(ADCT_ERANGE, "negative list length");
+        base[r] = tot;
+        tot += len[r];
+        kmax = std::max(kmax, len[r]);
+    }
+    *n_total = 0;
+    for (int r = 0; r < 8; ++r)
+        if (len[r] == 0) return ADCT_OK;
+    const int words = (kmax + 63) / 64;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<uint2> packed(tot);
+    for (int i = 0; i < tot; ++i) packed[i] = pack8(lists + 8 * int64_t(i));
+    DevBuf dl, dlen, dbase, dbits;
+    adct_status st;
+    if ((st = dalloc<uint2>(dl, tot))) return st;
+    if ((st = dalloc<int>(dlen, 8))) return st;
+    if ((st = dalloc<int>(dbase, 8))) return st;
+    const int64_t nbits = int64_t(28) * kmax * words;
+    if ((st = dalloc<unsigned long long>(dbits, nbits))) return st;
+    ADCT_HIP(hipMemcpyAsync(dl.p, packed.data(), sizeof(uint2) * tot, hipMemcpyHostToDevice, s));
+    ADCT_HIP(hipMemcpyAsync(dlen.p, len, sizeof(int) * 8, hipMemcpyHostToDevice, s));
+    ADCT_HIP(hipMemcpyAsync(dbase.p, base, sizeof(int) * 8, hipMemcpyHostToDevice, s));
+    const int64_t threads = int64_t(kmax) * words;
+    hipLaunchKernelGGL(k_ortho_bits, dim3(unsigned((threads + 255) / 256), 28), dim3(256), 0, s,
+                       (const uint2 *)dl.p, (const int *)dlen.p, (const int *)dbase.p, kmax, words,
+                       (unsigned long long *)dbits.p);
+    ADCT_HIP(hipGetLastError());
+    std::vector<unsigned long long> bits(nbits);
+    ADCT_HIP(hipMemcpyAsync(bits.data(), dbits.p, sizeof(unsigned long long) * nbits, hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipStreamSynchronize(s));
+    auto pair_index = [](int r1, int r2) {             // r1 < r2, row-major over the upper triangle
+        return r1 * 7 - r1 * (r1 - 1) / 2 + (r2 - r1 - 1);
+    };
+    // iterative depth-first search; cand[r] = AND of the orthogonality rows of
+    // the vectors chosen for rows < r
+    std::vector<std::vector<unsigned long long>> cand(8, std::vector<unsigned long long>(words));
+    int pos[8];
+    int64_t count = 0;
+    int r = 0;
+    for (int w = 0; w < words; ++w) cand[0][w] = ~0ull;
+    pos[0] = -1;
+    while (r >= 0) {
+        int a = pos[r] + 1;
+        while (a < len[r] && !((cand[r][a >> 6] >> (a & 63)) & 1ull)) ++a;
+        if (a >= len[r]) {
+            --r;
+            continue;
+        }
+        pos[r] = a;
+        if (r == 7) {
+            if (count < cap)
+                for (int q = 0; q < 8; ++q) out[count * 8 + q] = pos[q];
+            ++count;
+            continue;
+        }
+        const int nr = r + 1;
+        for (int w = 0; w < words; ++w) {
+            unsigned long long m = ~0ull;
+            for (int q = 0; q <= r; ++q)
+                m &= bits[(int64_t(pair_index(q, nr)) * kmax + pos[q]) * words + w];
+            cand[nr][w] = m;
+        }
+        pos[nr] = -1;
+        r = nr;
+    }
+    *n_total = count;
+    return ADCT_OK;
+}
+
+}  // extern "C"

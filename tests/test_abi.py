@@ -117,3 +117,26 @@ def test_tie_free_quantiser_steps_accepted():
         assert lib.adct_check_codec_args(tid, None, 10, step, 1) == -7
     assert lib.adct_check_codec_args(A.LO, None, 10, 0, 1) == -4
     assert lib.adct_check_codec_args(A.LO, None, 10, 0, 0) == 0
+
+
+def test_search_argument_errors_host_only():
+    lib = A.lib()
+    n = ctypes.c_int()
+    out = (A.Matrix * 4)()
+    bad_p = (ctypes.c_int8 * 2)(1, -1)                       # no zero
+    assert lib.adct_derive_transform(ctypes.cast(bad_p, ctypes.c_void_p), 2, 0, None, 0, 1, out, 4,
+                                     ctypes.byref(n), None, None, None, None) == -1
+    rep = (ctypes.c_int8 * 3)(0, 1, 1)                       # repeated entry
+    assert lib.adct_derive_transform(ctypes.cast(rep, ctypes.c_void_p), 3, 0, None, 0, 1, out, 4,
+                                     ctypes.byref(n), None, None, None, None) == -1
+    big = (ctypes.c_int8 * 3)(0, 1, 5)                       # entry beyond +-4
+    assert lib.adct_derive_transform(ctypes.cast(big, ctypes.c_void_p), 3, 0, None, 0, 1, out, 4,
+                                     ctypes.byref(n), None, None, None, None) == -3
+    p1 = (ctypes.c_int8 * 3)(0, 1, -1)
+    assert lib.adct_derive_transform(ctypes.cast(p1, ctypes.c_void_p), 3, 7, None, 0, 1, out, 4,
+                                     ctypes.byref(n), None, None, None, None) == -1   # bad mode
+    orders = (ctypes.c_uint8 * 6)(1, 2, 3, 5, 6, 6)
+    assert lib.adct_derive_transform(ctypes.cast(p1, ctypes.c_void_p), 3, 0,
+                                     ctypes.cast(orders, ctypes.c_void_p), 1, 1, out, 4,
+                                     ctypes.byref(n), None, None, None, None) == -1
+    assert lib.adct_search_topk(ctypes.cast(p1, ctypes.c_void_p), 3, 0, 1, FAKE, FAKE, FAKE, None) == -3
