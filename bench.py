@@ -105,7 +105,50 @@ def other_rows():
     res["search_topk_9pow8_k64"] = {"ms": round(t_scan * 1e3, 2), "candidates": 9 ** 8 - 1,
                                     "rows": 8, "Gcand_rows_per_s": round(8 * (9 ** 8 - 1) / t_scan / 1e9, 2),
                                     "tuples_ms": round(t_tup * 1e3, 2), "orthogonal_tuples": n64}
+    res.update(batch_row())
     return res
+
+
+def batch_row():
+    """The 45-image rate-distortion sweep as one autotuned graph replay."""
+    import numpy as np
+    import torch
+
+    import paper_1808_02950_amd as A
+    from synth import batch_images, batch_specs
+
+    imgs = batch_images(batch_specs())
+    parts, planes, off = [], [], 0
+    for im in imgs:
+        h, w = im.shape
+        parts.append(im.ravel())
+        planes.append((off, h, w, w))
+        off += h * w
+    base = torch.from_numpy(np.concatenate(parts)).cuda()
+    names = ["DCT", "T1", "LO", "T6", "RDCT", "T4"]
+    plan = A.BatchPlan(base, planes, names, 1, 63, autotune=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 5
+    for _ in range(reps):
+        plan.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    sse = plan.sse.cpu().numpy()
+    npix = np.array([im.size for im in imgs], dtype=np.float64)
+    psnr = (10 * np.log10(255.0 ** 2 * npix[:, None, None] / np.maximum(sse, 1))).mean(axis=0)
+    info = plan.info()
+    plan.close()
+    evals = len(imgs) * len(names) * 63
+    return {"batch_45img_6tf_r1_63": {
+        "ms": round(ms, 3), "evaluations": evals, "evaluations_per_s": round(evals / (ms / 1e3)),
+        "Gpixel_evals_per_s": round(off * len(names) * 63 / (ms / 1e3) / 1e9, 1),
+        "pixels": off, "schedule": info,
+        "mean_psnr_r10": {n: round(float(psnr[t, 9]), 4) for t, n in enumerate(names)}}}
 
 
 def main():

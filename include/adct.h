@@ -229,6 +229,39 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
 adct_status adct_orthogonal_tuples(const int8_t *lists, const int *len, int32_t *out, int64_t cap,
                                    int64_t *n_total, adct_stream_t stream);
 
+/* ---------------------------------------------------------------- batch */
+
+/* Rate-distortion sweep over many images (Sec. 6.1.1: per-image MSE / PSNR for
+ * each retained count r, averaged over an image set, for the exact DCT and the
+ * approximations).  For every image i, transform t and r in [r_lo, r_hi]:
+ * sse[(i * n_transforms + t) * (r_hi - r_lo + 1) + (r - r_lo)] = sum of
+ * squared errors of the rounded, clipped reconstruction (integer transforms:
+ * exact; ADCT_DCT: float64).  images[i] describes image i inside the device
+ * buffer `base` (offset, H, W, pitch; all multiples of 8).  Up to 64 images and
+ * 8 transforms (ADCT_DCT .. ADCT_T4) per call.  sse: device uint64, zeroed by
+ * the call.  The whole sweep is one persistent launch; wgs_per_cu (1..16)
+ * resident single-wave workgroups per compute unit; split (1..n_transforms)
+ * transform groups per 64-block tile. */
+adct_status adct_evaluate_batch(const uint8_t *base, const adct_plane *images, int n_images,
+                                const adct_transform_id *transforms, int n_transforms, int r_lo,
+                                int r_hi, uint64_t *sse, int wgs_per_cu, int split,
+                                adct_stream_t stream);
+
+/* A prepared sweep: the same computation captured once in a HIP graph (zero
+ * fill + persistent sweep) with its schedule picked by timing every candidate
+ * (wgs_per_cu, split) on the given input when autotune != 0 (this runs the
+ * sweep several times on `stream` and synchronises it).  All pointers are baked
+ * into the graph: the buffers must outlive the plan.  Launching replays the
+ * graph on any stream. */
+typedef struct adct_batch_plan_s *adct_batch_plan;
+adct_status adct_batch_plan_create(const uint8_t *base, const adct_plane *images, int n_images,
+                                   const adct_transform_id *transforms, int n_transforms, int r_lo,
+                                   int r_hi, uint64_t *sse, int autotune, adct_batch_plan *out,
+                                   adct_stream_t stream);
+adct_status adct_batch_plan_launch(adct_batch_plan plan, adct_stream_t stream);
+adct_status adct_batch_plan_info(adct_batch_plan plan, int *wgs_per_cu, int *split, double *tuned_ms);
+adct_status adct_batch_plan_destroy(adct_batch_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

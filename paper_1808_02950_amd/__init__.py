@@ -69,6 +69,13 @@ _SIGNATURES = {
                                    ctypes.POINTER(_I64), _P]),
     "adct_search_topk": (_I, [_P, _I, _I, _I, _P, _P, _P, _P]),
     "adct_orthogonal_tuples": (_I, [_P, ctypes.POINTER(_I), _P, _I64, ctypes.POINTER(_I64), _P]),
+    "adct_evaluate_batch": (_I, [_P, ctypes.POINTER(Plane), _I, _P, _I, _I, _I, _P, _I, _I, _P]),
+    "adct_batch_plan_create": (_I, [_P, ctypes.POINTER(Plane), _I, _P, _I, _I, _I, _P, _I,
+                                    ctypes.POINTER(_P), _P]),
+    "adct_batch_plan_launch": (_I, [_P, _P]),
+    "adct_batch_plan_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                  ctypes.POINTER(ctypes.c_double)]),
+    "adct_batch_plan_destroy": (_I, [_P]),
 }
 
 
@@ -293,3 +300,68 @@ def orthogonal_tuples(lists, cap: int = 1 << 20, stream=None):
     _check(lib().adct_orthogonal_tuples(flat.ctypes.data, lens, out.ctypes.data, cap,
                                         ctypes.byref(n), _stream(stream)))
     return out[:min(n.value, cap)], n.value
+
+
+# ---------------------------------------------------------------- batch
+
+def _tid_array(transforms):
+    arr = (ctypes.c_int * len(transforms))(*[_tid(t) for t in transforms])
+    return arr
+
+
+def evaluate_batch(base, images, transforms, r_lo: int = 1, r_hi: int = 63, sse=None,
+                   wgs_per_cu: int = 4, split: int = 1, stream=None):
+    """adct_evaluate_batch.  base: uint8 CUDA tensor holding every image;
+    images: list of (offset, H, W, pitch).  Returns the device table
+    (n_images, n_transforms, r_hi - r_lo + 1) int64 (uint64 values)."""
+    import torch
+    _need_cuda(base, torch.uint8, "base")
+    n = len(images)
+    if sse is None:
+        sse = torch.empty((n, len(transforms), r_hi - r_lo + 1), dtype=torch.int64, device=base.device)
+    tids = _tid_array(transforms)
+    _check(lib().adct_evaluate_batch(_ptr(base), planes_struct(images), n, ctypes.cast(tids, _P),
+                                     len(transforms), r_lo, r_hi, _ptr(sse), wgs_per_cu, split,
+                                     _stream(stream)))
+    return sse
+
+
+class BatchPlan:
+    """adct_batch_plan_*: the sweep captured in a HIP graph (optionally autotuned).
+    Keeps references to the buffers it was built on."""
+
+    def __init__(self, base, images, transforms, r_lo: int = 1, r_hi: int = 63, sse=None,
+                 autotune: bool = True, stream=None):
+        import torch
+        _need_cuda(base, torch.uint8, "base")
+        self.base = base
+        n = len(images)
+        self.sse = sse if sse is not None else torch.empty(
+            (n, len(transforms), r_hi - r_lo + 1), dtype=torch.int64, device=base.device)
+        self._planes = planes_struct(images)
+        self._tids = _tid_array(transforms)
+        self._h = _P()
+        _check(lib().adct_batch_plan_create(_ptr(base), self._planes, n, ctypes.cast(self._tids, _P),
+                                            len(transforms), r_lo, r_hi, _ptr(self.sse),
+                                            1 if autotune else 0, ctypes.byref(self._h),
+                                            _stream(stream)))
+
+    def launch(self, stream=None):
+        _check(lib().adct_batch_plan_launch(self._h, _stream(stream)))
+        return self.sse
+
+    def info(self):
+        w, s, ms = _I(), _I(), ctypes.c_double()
+        _check(lib().adct_batch_plan_info(self._h, ctypes.byref(w), ctypes.byref(s), ctypes.byref(ms)))
+        return {"wgs_per_cu": w.value, "split": s.value, "tuned_ms": ms.value}
+
+    def close(self):
+        if self._h:
+            lib().adct_batch_plan_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

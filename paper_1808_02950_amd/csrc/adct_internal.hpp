@@ -100,11 +100,16 @@ constexpr int kZZ[64] = {
     35, 42, 49, 56, 57, 50, 43, 36, 29, 22, 15, 23, 30, 37, 44, 51,
     58, 59, 52, 45, 38, 31, 39, 46, 53, 60, 61, 54, 47, 55, 62, 63};
 
-constexpr int zz_pos(int k, int l) {
-    for (int z = 0; z < 64; ++z)
-        if (kZZ[z] == 8 * k + l) return z;
-    return -1;
+struct ZZInv {
+    int pos[64];   // pos[8 * row + col] = zig-zag position
+};
+constexpr ZZInv make_zz_inv() {
+    ZZInv t{};
+    for (int z = 0; z < 64; ++z) t.pos[kZZ[z]] = z;
+    return t;
 }
+constexpr ZZInv kZZInv = make_zz_inv();
+constexpr int zz_pos(int k, int l) { return kZZInv.pos[8 * k + l]; }
 
 // Per-transform constants derived at compile time.
 template <int ID>

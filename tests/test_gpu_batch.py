@@ -1,0 +1,114 @@
+"""GPU rate-distortion sweep (one persistent launch, optionally replayed from a
+HIP graph) against the oracle's per-(image, transform, r) definition."""
+
+import numpy as np
+import pytest
+
+import paper_1808_02950_amd as A
+from oracle import batch as OB
+from oracle import codec as Co
+from oracle import matrices as M
+from synth import ar1_image, batch_images, batch_specs
+
+pytestmark = pytest.mark.gpu
+
+ALL = ["DCT", "T1", "LO", "T6", "RDCT", "T4", "T2"]
+
+
+def _pack(images, cuda, pad_pitch=0):
+    """Concatenate images into one device buffer; returns (tensor, planes)."""
+    import torch
+    planes, parts, off = [], [], 0
+    for img in images:
+        h, w = img.shape
+        pitch = w + pad_pitch
+        buf = np.zeros((h, pitch), dtype=np.uint8)
+        buf[:, :w] = img
+        parts.append(buf.ravel())
+        planes.append((off, h, w, pitch))
+        off += h * pitch
+    return torch.from_numpy(np.concatenate(parts)).to(cuda), planes
+
+
+def _check(gpu, ref, names):
+    for t, name in enumerate(names):
+        g, r = gpu[:, t, :].astype(np.int64), ref[:, t, :].astype(np.int64)
+        if name == "DCT":      # float64 reconstruction: equal unless a pixel sits on a half
+            assert np.all(np.abs(g - r) <= 1e-6 * r + 2), name
+        else:
+            assert np.array_equal(g, r), name
+
+
+@pytest.fixture(scope="module")
+def small_set():
+    return [ar1_image(72, 136, 0.9, seed=21), ar1_image(64, 64, 0.97, seed=22),
+            ar1_image(40, 48, 0.85, seed=23)]
+
+
+def test_batch_matches_oracle(cuda, small_set):
+    base, planes = _pack(small_set, cuda, pad_pitch=8)
+    sse = A.evaluate_batch(base, planes, ALL, 1, 64).cpu().numpy()
+    ref = OB.sse_table(small_set, ALL, 1, 64)
+    _check(sse, ref, ALL)
+    assert np.all(sse[:, 1:, -1] == 0)                     # lossless at r = 64
+
+
+@pytest.mark.parametrize("wgs,split", [(1, 1), (3, 7), (8, 1)])
+def test_batch_schedules_agree(cuda, small_set, wgs, split):
+    base, planes = _pack(small_set, cuda)
+    ref = A.evaluate_batch(base, planes, ALL, 3, 40).cpu().numpy()
+    got = A.evaluate_batch(base, planes, ALL, 3, 40, wgs_per_cu=wgs, split=split).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_batch_graph_replays(cuda, small_set):
+    import torch
+    base, planes = _pack(small_set, cuda)
+    names = ["DCT", "T1", "LO", "T6", "RDCT", "T4"]
+    eager = A.evaluate_batch(base, planes, names, 1, 63).cpu().numpy()
+    plan = A.BatchPlan(base, planes, names, 1, 63, autotune=True)
+    info = plan.info()
+    assert 1 <= info["wgs_per_cu"] <= 16 and info["split"] >= 1 and info["tuned_ms"] > 0
+    scratch = torch.empty(1 << 20, device=cuda)
+    for rep in range(4):
+        scratch.normal_()                                  # eager work between replays
+        torch.cuda.synchronize()
+        got = plan.launch().clone()
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), eager), rep
+    plan.close()
+
+
+def test_batch_45_images_sampled(cuda):
+    """The 45-image workload (uneven sizes up to 2048 x 1536): one plan, then
+    sampled (image, transform, r) entries against the oracle."""
+    specs = batch_specs()
+    images = batch_images(specs)
+    base, planes = _pack(images, cuda)
+    names = ["DCT", "T1", "LO", "T6", "RDCT", "T4"]
+    plan = A.BatchPlan(base, planes, names, 1, 63, autotune=False)
+    sse = plan.launch().cpu().numpy()
+    rng = np.random.default_rng(5)
+    small = sorted(range(len(images)), key=lambda i: images[i].size)[:6]
+    for _ in range(8):
+        i = int(rng.choice(small))
+        t = int(rng.integers(len(names)))
+        r = int(rng.integers(1, 64))
+        img = images[i]
+        ref = (Co.evaluate_dct(img, r) if names[t] == "DCT"
+               else Co.evaluate(img, M.TRANSFORMS[names[t]], r))["sse"]
+        if names[t] == "DCT":
+            assert abs(int(sse[i, t, r - 1]) - ref) <= 1e-6 * ref + 2
+        else:
+            assert int(sse[i, t, r - 1]) == ref, (i, names[t], r)
+    plan.close()
+
+
+def test_batch_argument_errors(cuda, small_set):
+    base, planes = _pack(small_set, cuda)
+    with pytest.raises(A.AdctError):
+        A.evaluate_batch(base, planes, ["T1"], 0, 10)
+    with pytest.raises(A.AdctError):
+        A.evaluate_batch(base, planes, ["CUSTOM"], 1, 10)
+    with pytest.raises(A.AdctError):
+        A.evaluate_batch(base, [(1, 8, 8, 8)], ["T1"], 1, 10)
