@@ -31,6 +31,7 @@ __all__ = [
     "video_base_planes",
     "video_frame",
     "patch_specs",
+    "filter_params",
 ]
 
 
@@ -181,3 +182,24 @@ def patch_specs(n: int, seed: int = 11, size: int = 64,
         table[k] = (k // per_image, i * size, j * size,
                     retain[int(rng.integers(0, len(retain)))])
     return images, table
+
+
+def filter_params(seed: int = 0, last_scale: float = 0.1, bias_scale: float = 0.0) -> np.ndarray:
+    """Seeded starting weights for the post-filter, flat float32 in the order
+    W1 (32,1,3,3), b1 (32), W2 (32,32,3,3), b2 (32), W3 (1,32,3,3), b3 (1).
+
+    Weights are uniform in +-sqrt(6 / fan_in) (fan_in = 9 input taps times
+    input channels), the last layer's scaled by `last_scale` so a fresh filter
+    starts close to the identity; biases uniform in +-bias_scale."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for shape, fan_in, scale in (((32, 1, 3, 3), 9, 1.0), ((32,), 0, 0.0),
+                                 ((32, 32, 3, 3), 288, 1.0), ((32,), 0, 0.0),
+                                 ((1, 32, 3, 3), 288, last_scale), ((1,), 0, 0.0)):
+        n = int(np.prod(shape))
+        if fan_in:
+            lim = math.sqrt(6.0 / fan_in) * scale
+        else:
+            lim = bias_scale
+        parts.append(rng.uniform(-lim, lim, size=n) if lim > 0 else np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
