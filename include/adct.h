@@ -262,6 +262,90 @@ adct_status adct_batch_plan_launch(adct_batch_plan plan, adct_stream_t stream);
 adct_status adct_batch_plan_info(adct_batch_plan plan, int *wgs_per_cu, int *split, double *tuned_ms);
 adct_status adct_batch_plan_destroy(adct_batch_plan plan);
 
+/* ---------------------------------------------------------------- learned post-filter
+ *
+ * Not part of the paper's method: a small network applied after decoding that
+ * removes part of the coding error the approximation leaves.  On a decoded
+ * 8-bit image x (one plane):
+ *   xn = (x - 128) / 64
+ *   a1 = relu(conv3x3(xn; W1, b1))   1 -> 32 channels
+ *   a2 = relu(conv3x3(a1; W2, b2))   32 -> 32
+ *   y  = xn + conv3x3(a2; W3, b3)    32 -> 1
+ *   output pixel = clip(round_half_even(128 + 64 y), 0, 255)
+ * Each 3x3 convolution is a cross-correlation that zero-pads its own input.
+ * Weights and activations enter the matrix cores as bfloat16 (round to
+ * nearest even), accumulation is float32, biases stay float32.
+ *
+ * Parameters: one flat float32 device vector of ADCT_FILTER_PARAMS values in
+ * PyTorch Conv2d order: W1 (32,1,3,3), b1 (32), W2 (32,32,3,3), b2 (32),
+ * W3 (1,32,3,3), b3 (1).  Training minimises the mean over all pixels of
+ * (y - (orig - 128) / 64)^2; gradients are taken with respect to the bfloat16
+ * weights, with the loss gradient and the masked input gradients rounded to
+ * bfloat16 where they enter the matrix cores.  All buffers are caller-owned
+ * device memory; calls enqueue on `stream` and do not synchronise. */
+#define ADCT_FILTER_PARAMS 9857
+
+/* Bytes of the packed form of the weights (operand order of the kernels). */
+int64_t adct_filter_packed_bytes(void);
+
+/* Packs params (device float32[ADCT_FILTER_PARAMS]) into `packed` (device,
+ * adct_filter_packed_bytes(), 16-byte aligned): bfloat16 weights in operand
+ * order plus the float32 biases.  The packed form is what adct_filter_apply reads. */
+adct_status adct_filter_pack(const float *params, void *packed, adct_stream_t stream);
+
+/* Workspace bytes adct_filter_grad / adct_filter_train_step need for n images
+ * of H x W (H a multiple of 16, W = 32 or 64); -1 when the shape is not
+ * supported. */
+int64_t adct_filter_workspace_bytes(int n, int H, int W);
+
+/* Loss and gradient on a batch.  recon, orig: device uint8 [n][H][W]
+ * (contiguous) decoded and original images.  grad: device float32
+ * [ADCT_FILTER_PARAMS] (overwritten); loss: device float32 scalar (nullable);
+ * y_out: device float32 [n][H][W] network output y (nullable).  The sums over
+ * pixels run in a fixed order, so repeated calls give identical results.
+ * Errors: ADCT_EINVAL null pointer, ADCT_EDIM unsupported shape, ADCT_ECAP
+ * workspace smaller than adct_filter_workspace_bytes. */
+adct_status adct_filter_grad(const float *params, const uint8_t *recon, const uint8_t *orig, int n, int H, int W,
+                             void *workspace, int64_t ws_bytes, float *grad, float *loss, float *y_out,
+                             adct_stream_t stream);
+
+/* One Adam step (Kingma and Ba, bias-corrected; `step` counts from 1) on
+ * params with moment buffers m and v (device float32[ADCT_FILTER_PARAMS], zero
+ * before the first step), in float32.  Errors: ADCT_ERANGE step < 1, lr < 0,
+ * beta outside [0, 1), eps <= 0. */
+adct_status adct_filter_adam(float *params, float *m, float *v, const float *grad, int step, float lr,
+                             float beta1, float beta2, float eps, adct_stream_t stream);
+
+/* adct_filter_grad (gradient kept in the workspace) followed by adct_filter_adam. */
+adct_status adct_filter_train_step(float *params, float *m, float *v, int step, float lr, float beta1, float beta2,
+                                   float eps, const uint8_t *recon, const uint8_t *orig, int n, int H, int W,
+                                   void *workspace, int64_t ws_bytes, float *loss, adct_stream_t stream);
+
+/* Inference on decoded frames: out = filter(frames), every plane of every
+ * frame, all three layers in one kernel without writing activations.  Planes
+ * as in adct_evaluate_stream (any H, W >= 1, pitch >= W); frames, out and
+ * orig use the same plane offsets and pitches with their own frame strides.
+ * out must not alias frames.  When sse (device uint64 [n_frames][n_planes],
+ * zeroed by the call) is given, it receives the squared error of out against
+ * orig.  Errors: ADCT_EINVAL null pointer / aliasing / sse without orig,
+ * ADCT_EDIM plane geometry or unaligned packed weights. */
+adct_status adct_filter_apply(const void *packed, const uint8_t *frames, int64_t frame_stride, int n_frames,
+                              const adct_plane *planes, int n_planes, uint8_t *out, int64_t frame_stride_out,
+                              const uint8_t *orig, int64_t frame_stride_orig, uint64_t *sse,
+                              adct_stream_t stream);
+
+/* Keep rule and fallback.  Frame f keeps its filtered planes (already in out)
+ * when the sum over planes of sse_filtered[f] is not larger than that of
+ * sse_reference[f] (same samples, so: PSNR at least the reference's, e.g. the
+ * exact DCT at the same r and quantiser); otherwise the plain reconstruction
+ * `plain` is copied into out.  keep (device uint8 [n_frames], nullable)
+ * receives the decision.  Plane W, pitch, offsets, strides and buffers must be
+ * multiples of 8 bytes (ADCT_EDIM). */
+adct_status adct_filter_select(const uint64_t *sse_filtered, const uint64_t *sse_reference, int n_frames,
+                               int n_planes, const uint8_t *plain, int64_t frame_stride_plain,
+                               const adct_plane *planes, uint8_t *out, int64_t frame_stride_out, uint8_t *keep,
+                               adct_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,16 @@ _SIGNATURES = {
     "adct_batch_plan_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                   ctypes.POINTER(ctypes.c_double)]),
     "adct_batch_plan_destroy": (_I, [_P]),
+    "adct_filter_packed_bytes": (_I64, []),
+    "adct_filter_pack": (_I, [_P, _P, _P]),
+    "adct_filter_workspace_bytes": (_I64, [_I, _I, _I]),
+    "adct_filter_grad": (_I, [_P, _P, _P, _I, _I, _I, _P, _I64, _P, _P, _P, _P]),
+    "adct_filter_adam": (_I, [_P, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, _P]),
+    "adct_filter_train_step": (_I, [_P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, _P, _P, _I, _I, _I, _P, _I64, _P, _P]),
+    "adct_filter_apply": (_I, [_P, _P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _I64, _P, _I64, _P, _P]),
+    "adct_filter_select": (_I, [_P, _P, _I, _I, _P, _I64, ctypes.POINTER(Plane), _P, _I64, _P, _P]),
 }
 
 
@@ -365,3 +375,114 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned post-filter
+
+FILTER_PARAMS = 9857
+
+
+def filter_pack(params, packed=None, stream=None):
+    """adct_filter_pack: float32 CUDA params (9857,) -> packed uint8 CUDA tensor."""
+    import torch
+    _need_cuda(params, torch.float32, "params")
+    if packed is None:
+        packed = torch.empty(lib().adct_filter_packed_bytes(), dtype=torch.uint8, device=params.device)
+    _check(lib().adct_filter_pack(_ptr(params), _ptr(packed), _stream(stream)))
+    return packed
+
+
+def filter_workspace(n: int, h: int, w: int, device="cuda"):
+    import torch
+    nb = lib().adct_filter_workspace_bytes(n, h, w)
+    if nb < 0:
+        raise AdctError(-2, f"unsupported training shape n={n} H={h} W={w}")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def filter_grad(params, recon, orig, workspace=None, want_y: bool = False, stream=None):
+    """adct_filter_grad on uint8 CUDA tensors (n, H, W).  Returns (grad, loss, y)
+    as CUDA tensors (y None unless want_y); does not synchronise."""
+    import torch
+    _need_cuda(params, torch.float32, "params")
+    _need_cuda(recon, torch.uint8, "recon")
+    _need_cuda(orig, torch.uint8, "orig")
+    n, h, w = recon.shape
+    if orig.shape != recon.shape or not recon.is_contiguous() or not orig.is_contiguous():
+        raise ValueError("recon and orig must be contiguous tensors of one shape")
+    if workspace is None:
+        workspace = filter_workspace(n, h, w, recon.device)
+    grad = torch.empty(FILTER_PARAMS, dtype=torch.float32, device=recon.device)
+    loss = torch.empty(1, dtype=torch.float32, device=recon.device)
+    y = torch.empty((n, h, w), dtype=torch.float32, device=recon.device) if want_y else None
+    _check(lib().adct_filter_grad(_ptr(params), _ptr(recon), _ptr(orig), n, h, w, _ptr(workspace),
+                                  workspace.numel(), _ptr(grad), _ptr(loss), _ptr(y), _stream(stream)))
+    return grad, loss, y
+
+
+def filter_adam(params, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                eps: float = 1e-8, stream=None):
+    _check(lib().adct_filter_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), step, lr, beta1, beta2, eps,
+                                  _stream(stream)))
+
+
+class FilterTrainer:
+    """Adam training of the post-filter on device batches through
+    adct_filter_train_step.  params: float32 (9857,) numpy or CUDA tensor."""
+
+    def __init__(self, params, n: int, h: int, w: int, lr: float = 1e-3, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, device="cuda"):
+        import torch
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32) if not isinstance(params, torch.Tensor)
+                                      else params, dtype=torch.float32).to(device).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.ws = filter_workspace(n, h, w, device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.shape = (n, h, w)
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.step_count = 0
+
+    def step(self, recon, orig, stream=None):
+        """One step on a batch (uint8 CUDA (n, H, W)); returns the device loss
+        tensor of this batch (before the update); does not synchronise."""
+        if tuple(recon.shape) != self.shape or tuple(orig.shape) != self.shape:
+            raise ValueError(f"batch shape must be {self.shape}")
+        self.step_count += 1
+        _check(lib().adct_filter_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), self.step_count,
+                                            self.lr, self.beta1, self.beta2, self.eps, _ptr(recon), _ptr(orig),
+                                            *self.shape, _ptr(self.ws), self.ws.numel(), _ptr(self.loss),
+                                            _stream(stream)))
+        return self.loss
+
+    def packed(self, stream=None):
+        return filter_pack(self.params, stream=stream)
+
+
+def filter_apply(packed, frames, planes, out=None, orig=None, stream=None):
+    """adct_filter_apply over frames (uint8 CUDA (n_frames, frame_bytes)).
+    Returns (out, sse) -- sse (n_frames, n_planes) int64 when orig is given."""
+    import torch
+    _need_cuda(frames, torch.uint8, "frames")
+    nf = frames.shape[0]
+    if out is None:
+        out = torch.zeros_like(frames)
+    sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device) if orig is not None else None
+    arr = planes_struct(planes)
+    _check(lib().adct_filter_apply(_ptr(packed), _ptr(frames), frames.stride(0), nf, arr, len(planes), _ptr(out),
+                                   out.stride(0), _ptr(orig), orig.stride(0) if orig is not None else 0,
+                                   _ptr(sse), _stream(stream)))
+    return out, sse
+
+
+def filter_select(sse_filtered, sse_reference, plain, planes, out, keep=None, stream=None):
+    """adct_filter_select: frames whose filtered SSE exceeds the reference's get
+    the plain reconstruction copied into out.  Returns the keep flags (uint8)."""
+    import torch
+    nf = plain.shape[0]
+    if keep is None:
+        keep = torch.empty(nf, dtype=torch.uint8, device=plain.device)
+    arr = planes_struct(planes)
+    _check(lib().adct_filter_select(_ptr(sse_filtered), _ptr(sse_reference), nf, len(planes), _ptr(plain),
+                                    plain.stride(0), arr, _ptr(out), out.stride(0), _ptr(keep), _stream(stream)))
+    return keep
