@@ -151,6 +151,104 @@ def batch_row():
         "mean_psnr_r10": {n: round(float(psnr[t, 9]), 4) for t, n in enumerate(names)}}}
 
 
+FILTER_FLOP_PER_PX = 2 * (9 + 288 * 32 + 288)     # 19,584: forward, per output pixel
+
+
+def filter_images(n_train: int, n_val: int):
+    """Seeded AR(1) images the training / held-out patches are cut from (host)."""
+    from synth import patch_specs
+    t0 = time.perf_counter()
+    tr = patch_specs(n_train, seed=11)
+    va = patch_specs(n_val, seed=12)
+    log(f"filter patches: {n_train} training + {n_val} held-out in {time.perf_counter() - t0:.1f} s")
+    return tr, va
+
+
+def filter_row(data, steps, frames, recon, planes, sse_plain, sse_dct, npix, codec_ms):
+    """Train the post-filter on the GPU, then run it on the decoded stream."""
+    import numpy as np
+    import torch
+
+    import paper_1808_02950_amd as A
+    from synth import filter_params
+
+    (imgs, tab), (vimgs, vtab) = data
+    t0 = time.perf_counter()
+    rec, org = A.patch_pairs(imgs, tab)
+    vrec, vorg = A.patch_pairs(vimgs, vtab)
+    torch.cuda.synchronize()
+    log(f"patch pairs decoded in {time.perf_counter() - t0:.1f} s; training {steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    params, losses = A.train_filter(filter_params(0), rec, org, steps, batch=64, lr=1e-3, lr_final=1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    train_tflops = steps * 64 * 64 * 64 * 3 * FILTER_FLOP_PER_PX / (train_ms / 1e3) / 1e12
+    packed = A.filter_pack(params)
+
+    # held-out patches: PSNR with and without the filter, per retention level
+    n = len(vrec)
+    vr = torch.from_numpy(vrec.reshape(n, -1)).cuda()
+    vo = torch.from_numpy(vorg.reshape(n, -1)).cuda()
+    _, vs = A.filter_apply(packed, vr, [(0, 64, 64, 64)], orig=vo)
+    sf = vs.cpu().numpy()[:, 0].astype(np.float64)
+    sp = ((vrec.astype(np.int64) - vorg) ** 2).sum(axis=(1, 2)).astype(np.float64)
+    held = {}
+    for r in (6, 10, 16):
+        m = vtab[:, 3] == r
+        pf = 10 * math.log10(255.0 ** 2 * 4096 * m.sum() / sf[m].sum())
+        pp = 10 * math.log10(255.0 ** 2 * 4096 * m.sum() / sp[m].sum())
+        held[f"r{r}"] = {"plain": round(pp, 4), "filtered": round(pf, 4), "gain": round(pf - pp, 4)}
+
+    # the decoded 4K stream: filter, keep rule against the exact DCT, fallback
+    filt = torch.empty_like(recon)
+    sse_f = torch.empty_like(sse_plain)
+
+    def apply_once():
+        A.filter_apply(packed, recon, planes, out=filt, orig=frames)
+
+    A.filter_apply(packed, recon, planes, out=filt, orig=frames)
+    torch.cuda.synchronize()
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        apply_once()
+    e1.record()
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / reps
+    _, sse_f = A.filter_apply(packed, recon, planes, out=filt, orig=frames)
+    e0.record()
+    keep = A.filter_select(sse_f, sse_dct, recon, planes, filt)
+    e1.record()
+    torch.cuda.synchronize()
+    select_ms = e0.elapsed_time(e1)
+    samples = frames.numel()
+    sf, sp, sd = (x.cpu().numpy().sum(axis=1).astype(np.float64) for x in (sse_f, sse_plain, sse_dct))
+    tot = float(sum(npix))
+    ps = lambda v: float(np.mean(10 * np.log10(255.0 ** 2 * tot / np.maximum(v, 1))))
+    kept = keep.cpu().numpy().astype(bool)
+    final = np.where(kept, sf, sp)
+    return {
+        "network": "3x3 conv 1->32->32->1, ReLU, residual; bf16 operands, fp32 accumulation",
+        "train": {"patches": int(len(rec)), "steps": steps, "batch": 64, "ms": round(train_ms, 2),
+                  "ms_per_step": round(train_ms / steps, 4), "tflops_fwd_bwd": round(train_tflops, 1),
+                  "loss_first": round(float(losses[:20].mean()), 6),
+                  "loss_last": round(float(losses[-100:].mean()), 6)},
+        "held_out_psnr_db": held,
+        "stream": {"apply_ms": round(apply_ms, 3), "select_ms": round(select_ms, 3),
+                   "tflops": round(samples * FILTER_FLOP_PER_PX / (apply_ms / 1e3) / 1e12, 1),
+                   "peak_bf16_tflops": 2500.0,
+                   "psnr_plain": round(ps(sp), 4), "psnr_filtered": round(ps(sf), 4),
+                   "psnr_dct": round(ps(sd), 4), "psnr_output": round(ps(final), 4),
+                   "gain_vs_plain": round(ps(sf) - ps(sp), 4), "gain_vs_dct": round(ps(sf) - ps(sd), 4),
+                   "frames_kept": int(kept.sum()), "frames": int(len(kept)),
+                   "plain_Mpixel_per_s": round(samples / (codec_ms / 1e3) / 1e6, 1),
+                   "learned_Mpixel_per_s": round(samples / ((codec_ms + apply_ms + select_ms) / 1e3) / 1e6,
+                                                 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +257,9 @@ def main():
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--cpu-frames", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--filter-patches", type=int, default=200000,
+                    help="training patches of the post-filter (0 skips the filter row)")
+    ap.add_argument("--filter-steps", type=int, default=6000)
     ap.add_argument("--schedule", type=int, default=0,
                     help="resident workgroups per CU of the codec grid (0 = occupancy limit, "
                          "-1 = one tile per wave)")
@@ -168,6 +269,9 @@ def main():
               f"with no exchange beyond the per-frame SSE, which this build does not launch.",
               file=sys.stderr)
         sys.exit(2)
+
+    # training images are drawn before the GPU is touched
+    fdata = filter_images(args.filter_patches, 4096) if args.filter_patches else None
 
     import torch
 
@@ -280,6 +384,9 @@ def main():
                      "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
     }
     out["other_rows"] = other_rows()
+    if fdata is not None:
+        out["other_rows"]["postfilter"] = filter_row(fdata, args.filter_steps, frames, recon, planes, sse,
+                                                     sse_dct, npix, kernel_ms)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_frames, spec.n_frames), r, step)

@@ -486,3 +486,61 @@ def filter_select(sse_filtered, sse_reference, plain, planes, out, keep=None, st
     _check(lib().adct_filter_select(_ptr(sse_filtered), _ptr(sse_reference), nf, len(planes), _ptr(plain),
                                     plain.stride(0), arr, _ptr(out), out.stride(0), _ptr(keep), _stream(stream)))
     return keep
+
+
+def patch_pairs(images, table, transform="T1", quant_step: int = 0, size: int = 64, device="cuda"):
+    """Training pairs for the post-filter, decoded by this library's codec.
+
+    images: list of 2-D uint8 numpy arrays; table: int rows (image, y0, x0, r)
+    with (y0, x0) on the 8x8 grid.  Patch k is the size x size block of
+    images[image] at (y0, x0), coded with `transform` keeping r coefficients
+    (and `quant_step`).  Blocks are coded independently, so coding the patch
+    alone equals cutting it from the coded image.  Returns host uint8 arrays
+    (recon, orig) of shape (n, size, size)."""
+    import torch
+    table = np.asarray(table, dtype=np.int64)
+    n = len(table)
+    orig = np.empty((n, size, size), dtype=np.uint8)
+    for i in np.unique(table[:, 0]):
+        rows = np.nonzero(table[:, 0] == i)[0]
+        img = images[int(i)]
+        for k in rows:
+            y0, x0 = int(table[k, 1]), int(table[k, 2])
+            orig[k] = img[y0:y0 + size, x0:x0 + size]
+    order = np.argsort(table[:, 3], kind="stable")
+    od = torch.from_numpy(orig[order].reshape(n, size * size)).to(device)
+    rec = torch.empty_like(od)
+    start = 0
+    for r in np.unique(table[:, 3]):
+        cnt = int(np.sum(table[:, 3] == r))
+        evaluate_stream(od[start:start + cnt], [(0, size, size, size)], transform, int(r), quant_step,
+                        recon=rec[start:start + cnt])
+        start += cnt
+    out = np.empty_like(orig)
+    out[order] = rec.cpu().numpy().reshape(n, size, size)
+    return out, orig
+
+
+def train_filter(params, recon, orig, steps: int, batch: int = 64, lr: float = 1e-3, lr_final: float = 1e-4,
+                 seed: int = 0, device="cuda", log_every: int = 0):
+    """Adam training of the post-filter on the GPU.  recon, orig: host uint8
+    (n, H, W) pairs (see patch_pairs).  The pairs are shuffled once (seeded)
+    and uploaded; step s trains on the next contiguous batch (wrapping), with
+    the learning rate decayed geometrically from lr to lr_final.  Returns
+    (trained params as a CUDA float32 tensor, per-step losses as numpy)."""
+    import torch
+    n, h, w = recon.shape
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(n)
+    rd = torch.from_numpy(np.ascontiguousarray(recon[perm])).to(device)
+    od = torch.from_numpy(np.ascontiguousarray(orig[perm])).to(device)
+    tr = FilterTrainer(params, batch, h, w, lr=lr, device=device)
+    losses = torch.empty(steps, dtype=torch.float32, device=device)
+    decay = (lr_final / lr) ** (1.0 / max(1, steps - 1))
+    for s in range(steps):
+        b0 = (s * batch) % (n - batch + 1)
+        tr.lr = lr * decay ** s
+        loss = tr.step(rd[b0:b0 + batch], od[b0:b0 + batch])
+        losses[s:s + 1].copy_(loss)
+        if log_every and (s + 1) % log_every == 0:
+            print(f"step {s + 1}: loss {float(loss.item()):.6f}", flush=True)
+    return tr.params, losses.cpu().numpy()

@@ -253,3 +253,66 @@ def test_filter_argument_errors(cuda):
         A.filter_apply(packed, f, [(0, 8, 8, 7)])        # pitch < W
     with pytest.raises(A.AdctError):
         A.filter_apply(packed, f, [(0, 8, 8, 8)], out=f)  # in place
+
+
+def _held_out_psnr(packed, vrec, vorg, vtab, cuda):
+    n = len(vrec)
+    _, s = A.filter_apply(packed, _dev(vrec.reshape(n, -1), cuda), [(0, 64, 64, 64)],
+                          orig=_dev(vorg.reshape(n, -1), cuda))
+    sf = s.cpu().numpy()[:, 0].astype(np.float64)
+    sp = ((vrec.astype(np.int64) - vorg) ** 2).sum(axis=(1, 2)).astype(np.float64)
+    out = {}
+    for r in (6, 10, 16):
+        m = vtab[:, 3] == r
+        out[r] = 10 * np.log10(sp[m].sum() / sf[m].sum())      # filtered minus plain, dB
+    return out
+
+
+def test_training_gains_over_plain_decoding(cuda):
+    """Train on the GPU (T1-decoded patches at r in {6, 10, 16}) and measure the
+    PSNR gain over the plain reconstruction on held-out patches from other
+    images; the fresh network is near the identity and loses a little."""
+    from synth import patch_specs
+    imgs, tab = patch_specs(8192, seed=11)
+    vimgs, vtab = patch_specs(1024, seed=12)
+    rec, org = A.patch_pairs(imgs, tab)
+    vrec, vorg = A.patch_pairs(vimgs, vtab)
+    p0 = filter_params(0)
+    before = _held_out_psnr(A.filter_pack(_dev(p0, cuda)), vrec, vorg, vtab, cuda)
+    params, losses = A.train_filter(p0, rec, org, 1500, batch=64, lr=1e-3, lr_final=1e-4)
+    after = _held_out_psnr(A.filter_pack(params), vrec, vorg, vtab, cuda)
+    print("gain dB before", {r: round(v, 3) for r, v in before.items()},
+          "after", {r: round(v, 3) for r, v in after.items()},
+          f"loss {losses[:20].mean():.5f} -> {losses[-100:].mean():.5f}")
+    assert losses[-100:].mean() < 0.95 * losses[:20].mean()
+    assert all(v > 0.05 for v in after.values())
+    assert after[10] > 0.2 and after[6] > 0.2
+
+
+def test_stream_keep_rule_end_to_end(cuda):
+    """Decoded stream (T1, r = 10, step 16), filter, keep rule against the
+    exact DCT: each output frame is the filtered one exactly when its squared
+    error is not above the DCT's, else the plain reconstruction."""
+    import torch
+    spec = video_spec(n_frames=4, width=288, height=160, seed=5)
+    bases = video_base_planes(spec)
+    frames = _dev(np.stack([video_frame(spec, bases, f) for f in range(4)]), cuda)
+    planes = [(o, h, w, w) for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets)]
+    recon = torch.empty_like(frames)
+    sse_plain = A.evaluate_stream(frames, planes, "T1", 10, 16, recon=recon)
+    sse_dct = A.evaluate_stream(frames, planes, "DCT", 10, 16)
+    # two weight sets: identity (never better than the DCT here) and a random one
+    pd = F.unflatten(filter_params(2, bias_scale=0.02))
+    pd["W3"][:] = 0.0
+    pd["b3"][:] = 0.0
+    for p in (F.flatten(pd).astype(np.float32), filter_params(4)):
+        packed = A.filter_pack(_dev(p, cuda))
+        out, sse_f = A.filter_apply(packed, recon, planes, orig=frames)
+        filt = out.clone()
+        keep = A.filter_select(sse_f, sse_dct, recon, planes, out)
+        torch.cuda.synchronize()
+        want = sse_f.cpu().numpy().sum(axis=1) <= sse_dct.cpu().numpy().sum(axis=1)
+        assert keep.cpu().numpy().astype(bool).tolist() == want.tolist()
+        for f in range(4):
+            assert torch.equal(out[f], filt[f] if want[f] else recon[f])
+
