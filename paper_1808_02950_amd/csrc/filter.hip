@@ -565,23 +565,32 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     for (int e = tid; e < 288; e += 256) dst[kOffW3 + e] = red[e];
 }
 
-// fixed-order sums over workgroups: deterministic gradient and loss
+// fixed-order sums over workgroups: deterministic gradient and loss.  A block
+// takes 32 consecutive parameters; its 8 row groups each sum every 8th
+// partial row, and the 8 group sums are added in a fixed order.
+constexpr int kRedCols = 32, kRedGroups = 8;
 __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, int n_wg,
                                                 const float *__restrict__ part3, int n_w3, float inv_count,
                                                 float *__restrict__ grad, float *__restrict__ loss) {
-    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
+    __shared__ float sm[kRedGroups][kRedCols];
+    const int c = threadIdx.x % kRedCols, q = threadIdx.x / kRedCols;
+    const int p = int(blockIdx.x) * kRedCols + c;
+    float s = 0.f;
     if (p < kOffB3) {
-        float s = 0.f;
-        for (int w = 0; w < n_wg; ++w) s += part[int64_t(w) * kParams + p];
-        grad[p] = s;
-    } else if (p == kOffB3) {
-        float s = 0.f;
-        for (int w = 0; w < n_w3; ++w) s += part3[2 * w + 1];
-        grad[p] = s;
-    } else if (p == kParams && loss) {
-        float s = 0.f;
-        for (int w = 0; w < n_w3; ++w) s += part3[2 * w];
-        *loss = s * inv_count;
+#pragma unroll 4
+        for (int w = q; w < n_wg; w += kRedGroups) s += part[int64_t(w) * kParams + p];
+    } else if (p == kOffB3 || p == kParams) {
+        const int k = p == kOffB3 ? 1 : 0;
+        for (int w = q; w < n_w3; w += kRedGroups) s += part3[2 * w + k];
+    }
+    sm[q][c] = s;
+    __syncthreads();
+    if (q == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < kRedGroups; ++k) t += sm[k][c];
+        if (p < kParams) grad[p] = t;
+        else if (p == kParams && loss) *loss = t * inv_count;
     }
 }
 
@@ -915,7 +924,7 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     WgradArgs w1 = wa;
     w1.g = dz1; w1.x = recon;
     hipLaunchKernelGGL(k_wgrad1, dim3(L.n_wg), blk, lds, s, w1);
-    hipLaunchKernelGGL(k_reduce, dim3((kParams + 1 + 255) / 256), blk, 0, s, part, L.n_wg, part3, L.n_w3,
+    hipLaunchKernelGGL(k_reduce, dim3((kParams + 1 + kRedCols - 1) / kRedCols), blk, 0, s, part, L.n_wg, part3, L.n_w3,
                        float(1.0 / (double(n) * H * W)), grad, loss);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
