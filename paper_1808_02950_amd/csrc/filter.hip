@@ -641,52 +641,71 @@ struct Ctx {
     uint32_t pre[3];      // prefetched x rows (same lane layout)
     uint32_t opre[3];     // prefetched original pixels of future output rows
     uint32_t sse;
+    // uniform row pointers at the column of lane offset 0, advanced by one row per step
+    const uint8_t *xrow;  // x row loaded next (row rho + 4 of the step)
+    const uint8_t *orow;  // original row loaded next (row rho + 1)
+    uint8_t *drow;        // output row written next (row rho - 2)
     const uint8_t *src, *org;
-    uint8_t *dst;
-    int H, W, pitch, y0, ccol, lsh, n, g;
-    bool edge, ok1[3], ok2, okout;
+    int64_t pitch;
+    int H, W, y0, ccol, lsh, n, g, xoff, ooff, bsrc;
+    bool ok1[3], ok2, okout, xok;
 };
 
-__device__ __forceinline__ uint32_t load_xrow(const Ctx &c, int row, int lane) {
-    const int col = c.ccol - 2 + lane;   // lane L holds column (first a2 column) - 2 + L
-    uint32_t v = 0;
-    if (lane < 20 && row >= 0 && row < c.H && col >= 0 && col < c.W)
-        v = uint32_t(c.src[int64_t(row) * c.pitch + col] - 128) & 0xffu;
-    return v;
+// x row `row` (EDGE: any row; zero outside the image) at column ccol - 2 + min(lane, 19)
+template <bool EDGE>
+__device__ __forceinline__ uint32_t load_x(Ctx &c, int row) {
+    if constexpr (!EDGE) {
+        const uint32_t v = c.xrow[c.xoff];
+        c.xrow += c.pitch;
+        return (v - 128u) & 0xffu;
+    } else {
+        const int rr = min(max(row, 0), c.H - 1);
+        const uint32_t v = c.src[int64_t(rr) * c.pitch + c.xoff];
+        return (c.xok && row == rr) ? (v - 128u) & 0xffu : 0u;
+    }
 }
-__device__ __forceinline__ uint32_t load_orig(const Ctx &c, int row) {
-    uint32_t v = 0;
-    if (c.org && c.okout && row >= 0 && row < c.H) v = c.org[int64_t(row) * c.pitch + c.ccol + c.n];
-    return v;
+template <bool EDGE>
+__device__ __forceinline__ uint32_t load_o(Ctx &c, int row) {
+    if constexpr (!EDGE) {
+        const uint32_t v = c.orow[c.ooff];
+        c.orow += c.pitch;
+        return v;
+    } else {
+        const int rr = min(max(row, 0), c.H - 1);
+        return c.org[int64_t(rr) * c.pitch + c.ooff];
+    }
 }
 
-template <int P>
-__device__ __forceinline__ void apply_step(Ctx &c, int s, int lane) {
+// One a1 row step.  P = s mod 3 (accumulator slots), A2: an a2 row completes,
+// EMIT: an output row completes, PREF: prefetch for step s + 3.
+template <bool EDGE, int P, bool A2, bool EMIT, bool PREF>
+__device__ __forceinline__ void apply_step(Ctx &c, int s) {
     const int rho = c.y0 - 2 + s;   // a1 row of this step
     {
         const uint32_t cur = c.pre[P];
-        c.pre[P] = load_xrow(c, rho + 4, lane);
+        if constexpr (PREF) c.pre[P] = load_x<EDGE>(c, rho + 4);
         c.word = (c.word >> 8) | (cur << 24);
     }
     // original pixel of output row rho - 2; prefetch the one three steps on
     const uint32_t o = c.opre[P];
-    c.opre[P] = load_orig(c, rho + 1);
+    if constexpr (PREF) c.opre[P] = load_o<EDGE>(c, rho + 1);
     // layer-1 B operands: slot (g, j) = xn at (rho + g - 1, column + dx + j - 1)
     float v[5];
     int w2 = 0;
 #pragma unroll
-    for (int o = 0; o < 5; ++o) {
-        const int w = __shfl(int(c.word), c.n + o, 64);
-        if (o == 2) w2 = w;
-        v[o] = float(int(uint32_t(w) << c.lsh) >> 24);
+    for (int q = 0; q < 5; ++q) {
+        const int w = __shfl(int(c.word), c.n + q, 64);
+        if (q == 2) w2 = w;
+        v[q] = float(int(uint32_t(w) << c.lsh) >> 24);
     }
-    const bool row1 = rho >= 0 && rho < c.H;
     uint4 B2[3];
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
         const uint2 B1 = {pack2(v[dx], v[dx + 1]), pack2(v[dx + 2], 0.f)};
         uint4 u = pack_relu(mma16(c.F1[0], B1, c.b1v[0]), mma16(c.F1[1], B1, c.b1v[1]));
-        if (!row1 || (c.edge && !c.ok1[dx])) u = uint4{0u, 0u, 0u, 0u};
+        if constexpr (EDGE) {
+            if (rho < 0 || rho >= c.H || !c.ok1[dx]) u = uint4{0u, 0u, 0u, 0u};
+        }
         B2[dx] = u;
     }
     // layer 2: a1 row rho feeds a2 rows rho + 1 - dy, slot (a2 row - y0 + 1) mod 3
@@ -701,11 +720,13 @@ __device__ __forceinline__ void apply_step(Ctx &c, int s, int lane) {
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) c.acc2[S2][h] = mma32(c.F2[6 + dx][h], B2[dx], c.acc2[S2][h]);
     }
-    if (s < 2) return;
+    if constexpr (!A2) return;
     // a2 row rho - 1 is complete
-    const int r2 = rho - 1;
     uint4 u = pack_relu(c.acc2[S2][0], c.acc2[S2][1]);
-    if (r2 < 0 || r2 >= c.H || (c.edge && !c.ok2)) u = uint4{0u, 0u, 0u, 0u};
+    if constexpr (EDGE) {
+        const int r2 = rho - 1;
+        if (r2 < 0 || r2 >= c.H || !c.ok2) u = uint4{0u, 0u, 0u, 0u};
+    }
     const uint4 uL = {uint32_t(__builtin_amdgcn_update_dpp(0, int(u.x), 0x111, 0xf, 0xf, true)),
                       uint32_t(__builtin_amdgcn_update_dpp(0, int(u.y), 0x111, 0xf, 0xf, true)),
                       uint32_t(__builtin_amdgcn_update_dpp(0, int(u.z), 0x111, 0xf, 0xf, true)),
@@ -717,18 +738,62 @@ __device__ __forceinline__ void apply_step(Ctx &c, int s, int lane) {
     c.acc3 = mma32(c.F3[0], uL, c.acc3);
     c.acc3 = mma32(c.F3[1], u, c.acc3);
     c.acc3 = mma32(c.F3[2], uR, c.acc3);
-    // output row rho - 2 is complete (register 2)
-    const int yo = rho - 2;
-    if (s >= 4 && yo < c.H && c.okout) {
-        const float xc = float((int(uint32_t(w2) << 24) >> 24) + 128);   // byte 0: row rho - 2, this lane's column
+    if constexpr (EMIT) {
+        // output row rho - 2 is complete (register 2)
+        const int yo = rho - 2;
+        bool live = c.okout;
+        if constexpr (EDGE) live = live && yo < c.H;
+        const float xc = float((int(uint32_t(w2) << 24) >> 24) + 128);   // byte 0: row rho - 2
         const float val = __builtin_rintf(fmaf(64.f, c.acc3[2] + c.b3, xc));
         const uint32_t pix = uint32_t(fminf(fmaxf(val, 0.f), 255.f));
-        c.dst[int64_t(yo) * c.pitch + c.ccol + c.n] = uint8_t(pix);
+        if constexpr (EDGE) {
+            if (live) c.drow[int64_t(yo - c.y0) * c.pitch + c.ooff] = uint8_t(pix);
+        } else {
+            // every lane stores the byte of column ccol + ooff, taken from the
+            // lane that owns it: lanes sharing an address write the same value
+            c.drow[c.ooff] = uint8_t(__shfl(int(pix), c.bsrc, 64));
+            c.drow += c.pitch;
+        }
         const int d = int(pix) - int(o);
-        c.sse += uint32_t(d * d);
+        c.sse += live ? uint32_t(d * d) : 0u;
     }
     c.acc3 = f32x4{0.f, c.acc3[0], c.acc3[1], 0.f};
 }
+
+// The 36 steps of one 32-row item: four prologue steps, nine unrolled triples,
+// five epilogue steps (the last three need no prefetch).  Row pointers (c.drow
+// set by the caller) advance one row per load / store on the interior path.
+template <bool EDGE>
+__device__ __forceinline__ void apply_item(Ctx &c) {
+    c.sse = 0;
+    c.acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
+    // x rows y0-4 .. y0-2 in bytes 1..3; rows y0-1 .. y0+1 prefetched for steps 0..2
+    c.xrow = c.src + int64_t(c.y0 - 4) * c.pitch;
+    c.orow = c.org + int64_t(c.y0 - 4) * c.pitch;
+    const uint32_t r0 = load_x<EDGE>(c, c.y0 - 4);
+    const uint32_t r1 = load_x<EDGE>(c, c.y0 - 3);
+    const uint32_t r2 = load_x<EDGE>(c, c.y0 - 2);
+    c.word = (r0 << 8) | (r1 << 16) | (r2 << 24);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.pre[k] = load_x<EDGE>(c, c.y0 - 1 + k);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.opre[k] = load_o<EDGE>(c, c.y0 - 4 + k);
+    apply_step<EDGE, 0, false, false, true>(c, 0);
+    apply_step<EDGE, 1, false, false, true>(c, 1);
+    apply_step<EDGE, 2, true, false, true>(c, 2);
+    apply_step<EDGE, 0, true, false, true>(c, 3);
+    for (int s = 4; s < 31; s += 3) {
+        apply_step<EDGE, 1, true, true, true>(c, s);
+        apply_step<EDGE, 2, true, true, true>(c, s + 1);
+        apply_step<EDGE, 0, true, true, true>(c, s + 2);
+    }
+    apply_step<EDGE, 1, true, true, true>(c, 31);
+    apply_step<EDGE, 2, true, true, true>(c, 32);
+    apply_step<EDGE, 0, true, true, false>(c, 33);
+    apply_step<EDGE, 1, true, true, false>(c, 34);
+    apply_step<EDGE, 2, true, true, false>(c, 35);
+}
+static_assert(kChunkRows == 32, "the step schedule of apply_item covers 36 steps");
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply(const ApplyArgs a) {
     const int lane = threadIdx.x & 63;
@@ -766,10 +831,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         c.pitch = P.pitch;
         c.y0 = chunk * kChunkRows;
         c.ccol = strip * kStripOut - 1;   // column of lane n = 0 for a2 and the output
-        c.src = a.in + int64_t(f) * a.fs_in + P.off;
-        c.dst = a.out + int64_t(f) * a.fs_out + P.off;
-        c.org = a.orig ? a.orig + int64_t(f) * a.fs_orig + P.off : nullptr;
-        c.edge = !(c.ccol - 1 >= 0 && c.ccol + 16 < c.W);
+        const bool interior = c.y0 >= 3 && c.y0 + 34 < c.H && c.ccol - 2 >= 0 && c.ccol + 17 < c.W;
+        const int xl = min(lane, 19);
+        const int on = min(max(c.n, 1), kStripOut);
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
             const int col = c.ccol + c.n + dx - 1;
@@ -777,20 +841,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         c.ok2 = c.ccol + c.n >= 0 && c.ccol + c.n < c.W;
         c.okout = c.g == 0 && c.n >= 1 && c.n <= kStripOut && c.ccol + c.n < c.W;
-        c.sse = 0;
-        c.acc3 = f32x4{0.f, 0.f, 0.f, 0.f};
-        // x rows y0-4 .. y0-2 in bytes 1..3; rows y0-1 .. y0+1 prefetched for steps 0..2
-        c.word = (load_xrow(c, c.y0 - 4, lane) << 8) | (load_xrow(c, c.y0 - 3, lane) << 16) |
-                 (load_xrow(c, c.y0 - 2, lane) << 24);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            c.pre[k] = load_xrow(c, c.y0 - 1 + k, lane);
-            c.opre[k] = load_orig(c, c.y0 - 4 + k);
-        }
-        for (int s = 0; s < kChunkRows + 4; s += 3) {
-            apply_step<0>(c, s, lane);
-            apply_step<1>(c, s + 1, lane);
-            apply_step<2>(c, s + 2, lane);
+        const uint8_t *fsrc = a.in + int64_t(f) * a.fs_in + P.off;
+        // without originals the loads read the input (valid memory) and no error is kept
+        const uint8_t *forg = a.orig ? a.orig + int64_t(f) * a.fs_orig + P.off : fsrc;
+        uint8_t *fdst = a.out + int64_t(f) * a.fs_out + P.off;
+        if (interior) {
+            // row pointers at column ccol - 2 (x) and ccol (orig, out); lane offsets in range
+            c.xoff = xl;
+            c.ooff = on;
+            c.bsrc = on;
+            c.src = fsrc + (c.ccol - 2);
+            c.org = forg + c.ccol;
+            c.xok = true;
+            c.drow = fdst + c.ccol + int64_t(c.y0) * c.pitch;
+            apply_item<false>(c);
+        } else {
+            // clamped columns; out-of-image values are zeroed by the masks
+            const int xc = c.ccol - 2 + xl;
+            c.xok = xc >= 0 && xc < c.W;
+            c.xoff = min(max(xc, 0), c.W - 1);
+            c.ooff = min(max(c.ccol + on, 0), c.W - 1);
+            c.src = fsrc;
+            c.org = forg;
+            c.drow = fdst + int64_t(c.y0) * c.pitch;
+            apply_item<true>(c);
         }
         if (a.sse) {
             uint32_t e = c.sse;
@@ -800,7 +874,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
     }
 }
-static_assert((kChunkRows + 4) % 3 == 0, "steps per item are unrolled by three");
 
 __global__ void k_zero_sse(unsigned long long *p, int n) {
     const int i = int(blockIdx.x) * 256 + int(threadIdx.x);
