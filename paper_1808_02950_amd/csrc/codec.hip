@@ -382,31 +382,58 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
             if (active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + x * P.pitch_out));
         }
     } else {
-        // dequantised B = step q, A = C_hat^T B C_hat in float64
-        double U[8][8];
+        // dequantised B = step q, A = C_hat^T B C_hat in float64.  The column
+        // pass runs over row pairs (x, 7 - x): row k of T is symmetric for even
+        // k and antisymmetric for odd k, so U[x][l] = e + o and
+        // U[7 - x][l] = e - o with e, o the even- and odd-k sums.  Only two rows
+        // of the intermediate are live at a time.
+        double Yd[KB][KB];
 #pragma unroll
-        for (int l = 0; l < KB; ++l) {
-            double yin[8], xo[8];
+        for (int k = 0; k < KB; ++k)
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                yin[k] = (k < KB && k + l <= BAND)
-                             ? double(C[k][l] * a.step) * Tf<ID>::skl(k, l) : 0.0;
-            inv8<ID, KB>(yin, xo, BAND - l);
+            for (int l = 0; l < KB; ++l)
+                Yd[k][l] = (k + l <= BAND) ? double(C[k][l] * a.step) * Tf<ID>::skl(k, l) : 0.0;
 #pragma unroll
-            for (int x = 0; x < 8; ++x) U[x][l] = xo[x];
-        }
+        for (int x = 0; x < 4; ++x) {
+            double yin0[8], yin1[8];
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            double yin[8], xo[8];
+            for (int l = 0; l < 8; ++l) {
+                yin0[l] = 0.0;
+                yin1[l] = 0.0;
+            }
 #pragma unroll
-            for (int l = 0; l < 8; ++l) yin[l] = (l < KB) ? U[x][l] : 0.0;
-            inv8<ID, KB>(yin, xo);
-            int q[8];
+            for (int l = 0; l < KB; ++l) {
+                double e = 0.0, o = 0.0;
+                bool he = false, ho = false;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) q[m] = clamp255(rne_i32(xo[m]));
-            const u32x2 v = emit_row(q, MODE == kEvaluate ? pix[x][0] : 0u,
-                                     MODE == kEvaluate ? pix[x][1] : 0u, sq, cross);
-            if (active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + x * P.pitch_out));
+                for (int k = 0; k < KB; ++k) {
+                    if (k + l > BAND) continue;
+                    const int tk = Tf<ID>::t(k, x);
+                    if (tk == 0) continue;
+                    const double v = Yd[k][l];
+                    if (k & 1) {
+                        o = ho ? fma(double(tk), v, o) : double(tk) * v;
+                        ho = true;
+                    } else {
+                        e = he ? fma(double(tk), v, e) : double(tk) * v;
+                        he = true;
+                    }
+                }
+                yin0[l] = ho ? e + o : e;
+                yin1[l] = ho ? e - o : e;
+            }
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int xr = half ? 7 - x : x;
+                double xo[8];
+                inv8<ID, KB>(half ? yin1 : yin0, xo);
+                int q[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) q[m] = clamp255(rne_i32(xo[m]));
+                const u32x2 v = emit_row(q, MODE == kEvaluate ? pix[xr][0] : 0u,
+                                         MODE == kEvaluate ? pix[xr][1] : 0u, sq, cross);
+                if (active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + xr * P.pitch_out));
+            }
         }
     }
 
