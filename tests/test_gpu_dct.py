@@ -92,3 +92,30 @@ def test_dct_argument_errors(cuda):
     img = torch.zeros((16, 16), dtype=torch.uint8, device=cuda)
     with pytest.raises(A.AdctError):
         A.encode_blocks(img, "DCT", 10, 0, want_int=True)      # integer output needs a step
+
+
+def test_dct_full_4k_frame_sampled(cuda):
+    """The benchmark's launch configuration (one 3840 x 2160 4:2:0 frame, r = 10,
+    step 16) checked block by block against the float64 oracle on 400 sampled
+    blocks of every plane, plus each plane's squared error."""
+    import torch
+    spec = video_spec(n_frames=1, seed=4)
+    bases = video_base_planes(spec)
+    frame = video_frame(spec, bases, 0)
+    planes = [(o, h, w, w) for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets)]
+    d = _dev(frame[None], cuda)
+    recon = torch.empty_like(d)
+    sse = A.evaluate_stream(d, planes, "DCT", 10, 16, recon=recon).cpu().numpy()
+    rec = recon.cpu().numpy()[0]
+    rng = np.random.default_rng(5)
+    for k, ((h, w), o) in enumerate(zip(spec.plane_shapes, spec.plane_offsets)):
+        img = frame[o:o + h * w].reshape(h, w)
+        got = rec[o:o + h * w].reshape(h, w)
+        by = rng.integers(0, h // 8, 400)
+        bx = rng.integers(0, w // 8, 400)
+        for y, x in zip(by, bx):
+            blk = img[8 * y:8 * y + 8, 8 * x:8 * x + 8]
+            ref = Co.evaluate_dct(blk, 10, 16)
+            _check_recon(got[8 * y:8 * y + 8, 8 * x:8 * x + 8], ref["rec"], ref["real"])
+        full = int(np.sum((got.astype(np.int64) - img) ** 2))
+        assert int(sse[0, k]) == full

@@ -316,3 +316,60 @@ def test_stream_keep_rule_end_to_end(cuda):
         for f in range(4):
             assert torch.equal(out[f], filt[f] if want[f] else recon[f])
 
+
+
+def test_grad_full_training_batch(cuda):
+    """The training launch shape (64 patches of 64 x 64, as the benchmark's
+    steps): loss and every gradient group against the oracle on the full batch."""
+    import torch
+    from synth import patch_specs
+    imgs, tab = patch_specs(64, seed=21)
+    rec, org = A.patch_pairs(imgs, tab)          # decoded by the library, compared as inputs only
+    orig = org
+    recon = np.stack([Co.evaluate(o, M.T1, int(r))["rec"] for o, r in zip(orig, tab[:, 3])]).astype(np.uint8)
+    assert np.array_equal(recon, rec)            # the library's decode of the patches is the oracle's
+    p = filter_params(6, last_scale=1.0, bias_scale=0.05)
+    grad, loss, _ = A.filter_grad(_dev(p, cuda), _dev(recon, cuda), _dev(orig, cuda))
+    torch.cuda.synchronize()
+    rl, rg, _ = F.loss_and_grad(p, recon, orig)
+    assert abs(float(loss.item()) - rl) <= 1e-4 * rl
+    g, r = _groups(grad.cpu().numpy().astype(np.float64)), _groups(rg)
+    for name, _ in GROUPS:
+        assert np.abs(g[name] - r[name]).max() <= 1e-3 * np.abs(r[name]).max(), name
+
+
+def test_apply_full_4k_frame_sampled(cuda):
+    """One 3840 x 2160 4:2:0 frame in the benchmark's launch configuration;
+    about 300 output pixels (borders, corners, tile seams and random ones)
+    checked against the oracle on their exact receptive field: the output at
+    (y, x) depends on the input within 3 pixels, and clipping that window at
+    the image edge reproduces the per-layer zero padding there."""
+    import torch
+    spec = video_spec(n_frames=2, seed=9)
+    bases = video_base_planes(spec)
+    frames = np.stack([video_frame(spec, bases, f) for f in range(2)])
+    planes = [(o, h, w, w) for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets)]
+    p = filter_params(8, last_scale=1.0, bias_scale=0.05)
+    packed = A.filter_pack(_dev(p, cuda))
+    out, sse = A.filter_apply(packed, _dev(frames[:1], cuda), planes, orig=_dev(frames[1:], cuda))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    rng = np.random.default_rng(3)
+    for k, ((h, w), o) in enumerate(zip(spec.plane_shapes, spec.plane_offsets)):
+        img = frames[0, o:o + h * w].reshape(h, w)
+        res = got[o:o + h * w].reshape(h, w)
+        ys = [0, 1, 2, 31, 32, 33, h // 2, h - 3, h - 2, h - 1]
+        xs = [0, 1, 13, 14, 15, 27, 28, w // 2, w - 2, w - 1]
+        pts = [(y, x) for y in ys for x in xs] + [tuple(v) for v in
+                                                  zip(rng.integers(0, h, 30), rng.integers(0, w, 30))]
+        for y, x in pts:
+            y0, y1, x0, x1 = max(0, y - 3), min(h, y + 4), max(0, x - 3), min(w, x + 4)
+            win = img[y0:y1, x0:x1][None]
+            ref = F.apply(p, win)
+            bound = _y_bound(p, win)[0][0]
+            cy, cx = y - y0, x - x0
+            one = {"out": ref["out"][0][cy:cy + 1, cx:cx + 1], "real": ref["real"][0][cy:cy + 1, cx:cx + 1]}
+            _check_pixels(res[y:y + 1, x:x + 1], one, bound[cy:cy + 1, cx:cx + 1])
+        # the squared error the kernel reports is that of its own output
+        org = frames[1, o:o + h * w].reshape(h, w)
+        assert int(sse[0, k]) == int(np.sum((res.astype(np.int64) - org) ** 2))
