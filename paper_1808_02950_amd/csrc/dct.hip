@@ -67,7 +67,9 @@ __device__ __forceinline__ DTile dtile_of(const DctArgs &a, int gw, int n) {
     return t;
 }
 
-template <int MODE>
+// ONE: r <= 16, a single coefficient tile: every operand of K a lane needs
+// (16 forward, 16 inverse) is read from LDS once into registers.
+template <int MODE, bool ONE>
 __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
     __shared__ float kf[64 * 64];
     __shared__ float ki[64 * 64];
@@ -83,7 +85,16 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int total = a.n_frames * a.waves_per_frame;
-    const int nct = (a.r + 15) >> 4;                       // coefficient tiles
+    const int nct = ONE ? 1 : (a.r + 15) >> 4;             // coefficient tiles
+    float kfr[16], kir[16];
+    if constexpr (ONE) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) kfr[s] = kf[fwd_addr(n, 16 * (s >> 2) + 4 * g + (s & 3))];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) kir[4 * t + s] = ki[inv_addr(16 * t + n, 4 * g + s)];
+    }
     for (int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
          gw < total; gw += int(gridDim.x) * 4) {
         const DTile T = dtile_of(a, gw, n);
@@ -110,7 +121,7 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
 #pragma unroll
                 for (int s = 0; s < 16; ++s) {
                     const int p = 16 * (s >> 2) + 4 * g + (s & 3);
-                    const float av = kf[fwd_addr(16 * ct + n, p)];
+                    const float av = ONE ? kfr[s] : kf[fwd_addr(16 * ct + n, p)];
                     const float bv = float((px[s >> 2] >> (8 * (s & 3))) & 0xffu);
                     part[s >> 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, part[s >> 2], 0, 0, 0);
                 }
@@ -152,7 +163,7 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float av = ki[inv_addr(16 * t + n, 16 * ct + 4 * g + s)];
+                    const float av = ONE ? kir[4 * t + s] : ki[inv_addr(16 * t + n, 16 * ct + 4 * g + s)];
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, coef[s], acc[t], 0, 0, 0);
                 }
         }
@@ -187,8 +198,8 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
     }
 }
 
-template <int M>
-adct_status launch_dct_mode(const DctArgs &a, int total_waves, hipStream_t s) {
+template <int M, bool ONE>
+adct_status launch_dct_kernel(const DctArgs &a, int total_waves, hipStream_t s) {
     static thread_local int cached_dev = -1, cus = 0;
     int dev = 0;
     ADCT_HIP(hipGetDevice(&dev));
@@ -197,13 +208,18 @@ adct_status launch_dct_mode(const DctArgs &a, int total_waves, hipStream_t s) {
         cached_dev = dev;
     }
     int per_cu = 0;
-    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dct<M>, 256, 0));
+    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dct<M, ONE>, 256, 0));
     if (per_cu < 1) per_cu = 1;
     const int64_t want = (int64_t(total_waves) + 3) / 4;
     const int grid = int(std::min<int64_t>(want, int64_t(per_cu) * cus));
-    hipLaunchKernelGGL(k_dct<M>, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dct<M, ONE>), dim3(grid), dim3(256), 0, s, a);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
+}
+
+template <int M>
+adct_status launch_dct_mode(const DctArgs &a, int total_waves, hipStream_t s) {
+    return a.r <= 16 ? launch_dct_kernel<M, true>(a, total_waves, s) : launch_dct_kernel<M, false>(a, total_waves, s);
 }
 
 }  // namespace
