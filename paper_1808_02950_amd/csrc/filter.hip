@@ -566,9 +566,10 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
 }
 
 // fixed-order sums over workgroups: deterministic gradient and loss.  A block
-// takes 32 consecutive parameters; its 8 row groups each sum every 8th
-// partial row, and the 8 group sums are added in a fixed order.
-constexpr int kRedCols = 32, kRedGroups = 8;
+// takes 16 consecutive parameters; its 16 row groups each sum every 16th
+// partial row (all loads of a thread in flight together), and the 16 group
+// sums are added in a fixed order.
+constexpr int kRedCols = 16, kRedGroups = 16;
 __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, int n_wg,
                                                 const float *__restrict__ part3, int n_w3, float inv_count,
                                                 float *__restrict__ grad, float *__restrict__ loss) {
@@ -577,8 +578,15 @@ __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, 
     const int p = int(blockIdx.x) * kRedCols + c;
     float s = 0.f;
     if (p < kOffB3) {
-#pragma unroll 4
-        for (int w = q; w < n_wg; w += kRedGroups) s += part[int64_t(w) * kParams + p];
+        int w = q;
+        for (; w + 15 * kRedGroups < n_wg; w += 16 * kRedGroups) {
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = part[int64_t(w + k * kRedGroups) * kParams + p];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s += v[k];
+        }
+        for (; w < n_wg; w += kRedGroups) s += part[int64_t(w) * kParams + p];
     } else if (p == kOffB3 || p == kParams) {
         const int k = p == kOffB3 ? 1 : 0;
         for (int w = q; w < n_w3; w += kRedGroups) s += part3[2 * w + k];
