@@ -443,17 +443,19 @@ class FilterTrainer:
         self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
         self.step_count = 0
 
-    def step(self, recon, orig, stream=None):
-        """One step on a batch (uint8 CUDA (n, H, W)); returns the device loss
-        tensor of this batch (before the update); does not synchronise."""
+    def step(self, recon, orig, loss_out=None, stream=None):
+        """One step on a batch (uint8 CUDA (n, H, W)); the batch loss (before
+        the update) goes to loss_out (a one-element float32 CUDA tensor) or to
+        self.loss, which is returned; does not synchronise."""
         if tuple(recon.shape) != self.shape or tuple(orig.shape) != self.shape:
             raise ValueError(f"batch shape must be {self.shape}")
         self.step_count += 1
+        dst = self.loss if loss_out is None else loss_out
         _check(lib().adct_filter_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), self.step_count,
                                             self.lr, self.beta1, self.beta2, self.eps, _ptr(recon), _ptr(orig),
-                                            *self.shape, _ptr(self.ws), self.ws.numel(), _ptr(self.loss),
+                                            *self.shape, _ptr(self.ws), self.ws.numel(), _ptr(dst),
                                             _stream(stream)))
-        return self.loss
+        return dst
 
     def packed(self, stream=None):
         return filter_pack(self.params, stream=stream)
@@ -539,8 +541,7 @@ def train_filter(params, recon, orig, steps: int, batch: int = 64, lr: float = 1
     for s in range(steps):
         b0 = (s * batch) % (n - batch + 1)
         tr.lr = lr * decay ** s
-        loss = tr.step(rd[b0:b0 + batch], od[b0:b0 + batch])
-        losses[s:s + 1].copy_(loss)
+        loss = tr.step(rd[b0:b0 + batch], od[b0:b0 + batch], loss_out=losses[s:s + 1])
         if log_every and (s + 1) % log_every == 0:
             print(f"step {s + 1}: loss {float(loss.item()):.6f}", flush=True)
     return tr.params, losses.cpu().numpy()
