@@ -140,3 +140,43 @@ def test_search_argument_errors_host_only():
                                      ctypes.cast(orders, ctypes.c_void_p), 1, 1, out, 4,
                                      ctypes.byref(n), None, None, None, None) == -1
     assert lib.adct_search_topk(ctypes.cast(p1, ctypes.c_void_p), 3, 0, 1, FAKE, FAKE, FAKE, None) == -3
+
+
+def test_filter_argument_errors_host_only():
+    """Every filter entry point validates before any device work: empty
+    batches, unsupported shapes, small workspaces, bad optimiser settings,
+    aliasing and plane geometry."""
+    lib = A.lib()
+    F2 = ctypes.c_void_p(8192)
+    assert lib.adct_filter_packed_bytes() > 20992 * 2
+    assert lib.adct_filter_workspace_bytes(2, 64, 64) > 0
+    for n, h, w in [(0, 64, 64), (2, 40, 64), (2, 64, 48), (2, 64, 128), (2, 0, 64)]:
+        assert lib.adct_filter_workspace_bytes(n, h, w) == -1, (n, h, w)
+    need = lib.adct_filter_workspace_bytes(2, 32, 64)
+    assert lib.adct_filter_grad(FAKE, FAKE, F2, 0, 32, 64, FAKE, need, FAKE, None, None, None) == -3
+    assert lib.adct_filter_grad(FAKE, FAKE, F2, 2, 32, 48, FAKE, need, FAKE, None, None, None) == -2
+    assert lib.adct_filter_grad(FAKE, FAKE, F2, 2, 32, 64, FAKE, need - 1, FAKE, None, None, None) == -5
+    assert lib.adct_filter_grad(None, FAKE, F2, 2, 32, 64, FAKE, need, FAKE, None, None, None) == -1
+    for step, lr, b1, b2, eps in [(0, 1e-3, 0.9, 0.999, 1e-8), (1, -1.0, 0.9, 0.999, 1e-8),
+                                  (1, 1e-3, 1.0, 0.999, 1e-8), (1, 1e-3, 0.9, 0.999, 0.0)]:
+        assert lib.adct_filter_adam(FAKE, FAKE, FAKE, FAKE, step, lr, b1, b2, eps, None) == -3
+    planes = A.planes_struct([(0, 16, 16, 16)])
+    assert lib.adct_filter_apply(FAKE, FAKE, 256, 0, planes, 1, F2, 256, None, 0, None, None) == -3
+    assert lib.adct_filter_apply(FAKE, FAKE, 256, 1, planes, 5, F2, 256, None, 0, None, None) == -3
+    assert lib.adct_filter_apply(FAKE, FAKE, 256, 1, planes, 1, FAKE, 256, None, 0, None, None) == -1
+    assert lib.adct_filter_apply(FAKE, FAKE, 256, 1, planes, 1, F2, 256, None, 0, F2, None) == -1
+    assert lib.adct_filter_apply(ctypes.c_void_p(4100), FAKE, 256, 1, planes, 1, F2, 256, None, 0,
+                                 None, None) == -2
+    bad = A.planes_struct([(0, 16, 16, 15)])                       # pitch < W
+    assert lib.adct_filter_apply(FAKE, FAKE, 256, 1, bad, 1, F2, 256, None, 0, None, None) == -2
+    odd = A.planes_struct([(0, 16, 12, 16)])                       # select copies 8-byte words
+    assert lib.adct_filter_select(FAKE, FAKE, 1, 1, FAKE, 256, odd, F2, 256, None, None) == -2
+    assert lib.adct_filter_select(FAKE, FAKE, 0, 1, FAKE, 256, planes, F2, 256, None, None) == -3
+
+
+def test_batch_empty_and_oversized_sets():
+    lib = A.lib()
+    planes = A.planes_struct([(0, 16, 16, 16)])
+    tids = (ctypes.c_int * 1)(A.T1)
+    assert lib.adct_evaluate_batch(FAKE, planes, 0, tids, 1, 1, 63, FAKE, 4, 1, None) == -3
+    assert lib.adct_evaluate_batch(FAKE, planes, 1, tids, 0, 1, 63, FAKE, 4, 1, None) == -3

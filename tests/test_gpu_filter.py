@@ -158,7 +158,7 @@ def _check_pixels(out, ref, bound):
     return int((diff != 0).sum())
 
 
-@pytest.mark.parametrize("h,w", [(64, 64), (37, 45), (8, 5), (40, 30), (33, 200)])
+@pytest.mark.parametrize("h,w", [(64, 64), (37, 45), (8, 5), (40, 30), (33, 200), (1, 1), (1, 17), (19, 1)])
 def test_apply_matches_oracle(cuda, h, w):
     import torch
     orig = ar1_image(h, w, 0.9, seed=h * 1000 + w)
