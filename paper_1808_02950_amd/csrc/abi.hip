@@ -165,6 +165,7 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
     a->step = quant_step;
     a->inv_step_f = quant_step ? float(1.0 / quant_step) : 0.f;
     a->inv_step_d = quant_step ? 1.0 / quant_step : 0.0;
+    a->step_d = double(quant_step);
     return ADCT_OK;
 }
 

@@ -193,6 +193,7 @@ struct CodecArgs {
     int32_t step;        // quantiser step (0: zonal coding only)
     float inv_step_f;    // 1 / step
     double inv_step_d;   // 1 / step
+    double step_d;       // step
 };
 
 struct DctArgs {

@@ -392,7 +392,9 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
         for (int k = 0; k < KB; ++k)
 #pragma unroll
             for (int l = 0; l < KB; ++l)
-                Yd[k][l] = (k + l <= BAND) ? double(C[k][l] * a.step) * Tf<ID>::skl(k, l) : 0.0;
+                // q step is exact in float64 (|q| < 2^15, step < 2^16) and needs no
+                // quarter-rate 32-bit integer multiply
+                Yd[k][l] = (k + l <= BAND) ? double(C[k][l]) * a.step_d * Tf<ID>::skl(k, l) : 0.0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             double yin0[8], yin1[8];
