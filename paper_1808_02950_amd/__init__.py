@@ -460,6 +460,27 @@ class FilterTrainer:
     def packed(self, stream=None):
         return filter_pack(self.params, stream=stream)
 
+    def save(self, path: str):
+        """Checkpoint: float32 master weights, Adam moments, step count and
+        hyper-parameters in a numpy .npz file (plain arrays, no pickled objects)."""
+        np.savez(path, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+                 step_count=np.int64(self.step_count), shape=np.array(self.shape, dtype=np.int64),
+                 hyper=np.array([self.lr, self.beta1, self.beta2, self.eps], dtype=np.float64))
+
+    @classmethod
+    def load(cls, path: str, device="cuda"):
+        """Resume from a checkpoint written by save(); continuing gives the same
+        weights as an uninterrupted run (the gradient is deterministic)."""
+        import torch
+        with np.load(path, allow_pickle=False) as z:
+            n, h, w = (int(x) for x in z["shape"])
+            lr, b1, b2, eps = (float(x) for x in z["hyper"])
+            tr = cls(z["params"], n, h, w, lr=lr, beta1=b1, beta2=b2, eps=eps, device=device)
+            tr.m.copy_(torch.from_numpy(z["m"]))
+            tr.v.copy_(torch.from_numpy(z["v"]))
+            tr.step_count = int(z["step_count"])
+        return tr
+
 
 def filter_apply(packed, frames, planes, out=None, orig=None, stream=None):
     """adct_filter_apply over frames (uint8 CUDA (n_frames, frame_bytes)).

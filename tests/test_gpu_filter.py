@@ -373,3 +373,33 @@ def test_apply_full_4k_frame_sampled(cuda):
         # the squared error the kernel reports is that of its own output
         org = frames[1, o:o + h * w].reshape(h, w)
         assert int(sse[0, k]) == int(np.sum((res.astype(np.int64) - org) ** 2))
+
+
+def test_checkpoint_resume_is_exact(cuda, tmp_path):
+    """Train 10 steps, checkpoint, resume in a new trainer for 10 more: the
+    weights and moments equal those of 20 uninterrupted steps bit for bit."""
+    import torch
+    from synth import patch_specs
+    imgs, tab = patch_specs(256, seed=31)
+    rec, org = A.patch_pairs(imgs, tab)
+    rd, od = _dev(rec, cuda), _dev(org, cuda)
+    p0 = filter_params(3)
+
+    def run(tr, s0, s1):
+        for s in range(s0, s1):
+            b = (s * 32) % 224
+            tr.step(rd[b:b + 32], od[b:b + 32])
+
+    full = A.FilterTrainer(p0, 32, 64, 64, lr=2e-3)
+    run(full, 0, 20)
+    half = A.FilterTrainer(p0, 32, 64, 64, lr=2e-3)
+    run(half, 0, 10)
+    path = str(tmp_path / "filter.npz")
+    half.save(path)
+    resumed = A.FilterTrainer.load(path, device=cuda)
+    run(resumed, 10, 20)
+    torch.cuda.synchronize()
+    assert resumed.step_count == 20
+    for a, b in ((full.params, resumed.params), (full.m, resumed.m), (full.v, resumed.v)):
+        assert torch.equal(a, b)
+    assert not torch.equal(full.params, torch.from_numpy(p0).to(cuda))
