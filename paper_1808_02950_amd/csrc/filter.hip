@@ -653,10 +653,14 @@ struct Ctx {
     const uint8_t *xrow;  // x row loaded next (row rho + 4 of the step)
     const uint8_t *orow;  // original row loaded next (row rho + 1)
     uint8_t *drow;        // output row written next (row rho - 2)
+    // interior tiles: row 0 of the plane at column ccol - 2 (x) / ccol (original);
+    // border tiles: the plane origins (columns are clamped per lane)
     const uint8_t *src, *org;
     int64_t pitch;
-    int H, W, y0, ccol, lsh, n, g, xoff, ooff, bsrc;
-    bool ok1[3], ok2, okout, xok;
+    int H, W, y0, ccol, lsh, n, g;
+    int xoff, ooff, bsrc;   // lane offsets of the x window, the output column, its owner lane
+    bool ok1[3], ok2;       // border tiles: a1 columns (per shift) and the a2 column inside the plane
+    bool okout, xok;        // this lane writes an output pixel; its x column is inside the plane
 };
 
 // x row `row` (EDGE: any row; zero outside the image) at column ccol - 2 + min(lane, 19)
