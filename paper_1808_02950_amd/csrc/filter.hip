@@ -342,14 +342,16 @@ struct WgradArgs {
     const uint16_t *act;   // input-side activation [n][H][W][32]
     const uint8_t *x;      // decoded images (first layer)
     float *part;           // [workgroup][kParams]
-    int H, W, bands;
+    int H, W, lw, bands;   // W = 1 << lw
 };
 
 // rows [row0, row0 + nrows) of a 32-channel map -> T[slot * sstride + r * rpitch + coff + px]
+// (W = 1 << lw)
 __device__ __forceinline__ void stage32(uint16_t *T, int sstride, int rpitch, int coff, const uint16_t *src,
-                                        int img, int row0, int nrows, int H, int W) {
-    for (int c = int(threadIdx.x); c < nrows * 4 * W; c += 256) {
-        const int px = c % W, rest = c / W, q = rest & 3, r = rest >> 2;
+                                        int img, int row0, int nrows, int H, int lw) {
+    const int W = 1 << lw;
+    for (int c = int(threadIdx.x); c < (nrows * 4) << lw; c += 256) {
+        const int px = c & (W - 1), rest = c >> lw, q = rest & 3, r = rest >> 2;
         const int row = row0 + r;
         uint4 v = {0u, 0u, 0u, 0u};
         if (row >= 0 && row < H)
@@ -370,7 +372,9 @@ __device__ __forceinline__ int act_stride(int W) { return 6 * (W + 16) + 8; }
 
 constexpr uint32_t kOne2 = 0x3f803f80u;   // two bfloat16 ones
 
-// dW2[o][i][t] = sum_p dz2[o][p] a1[i][p + off_t];  db2[o] = sum_p dz2[o][p]
+// dW2[o][i][t] = sum_p dz2[o][p] a1[i][p + off_t];  db2[o] = sum_p dz2[o][p].
+// Wave w owns the output half oh = w / 2 and input half ih = w % 2 for all 9
+// taps and every pixel of the band, so the four waves write disjoint entries.
 __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     extern __shared__ uint4 smem4[];
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
@@ -379,72 +383,44 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     const int img = int(blockIdx.x) / a.bands, y0 = (int(blockIdx.x) % a.bands) * 16;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int oh = wave >> 1, ih = wave & 1;
     for (int c = tid; c < 32 * 6 * 16; c += 256) {
-        const int k = c & 15, r = (c >> 4) % 6, s = c / 96;
-        aT[s * AS + r * AP + (k < 8 ? k : W + k)] = 0;
+        const int k = c & 15, r = (c >> 4) % 6, sl = c / 96;
+        aT[sl * AS + r * AP + (k < 8 ? k : W + k)] = 0;
     }
-    f32x4 acc[9][2][2] = {};
-    f32x4 accb[2] = {};
+    f32x4 acc[9] = {};
+    f32x4 accb = {0.f, 0.f, 0.f, 0.f};
     const uint4 ones = {kOne2, kOne2, kOne2, kOne2};
-    const int cpr = W / 32;   // 32-pixel chunks per row
+    const int lcpr = a.lw - 5;   // log2 of the 32-pixel chunks per row
     for (int sb = 0; sb < 4; ++sb) {
         const int r0 = y0 + 4 * sb;
         __syncthreads();
-        stage32(dzT, DS, W, 0, a.g, img, r0, 4, a.H, W);
-        stage32(aT, AS, AP, 8, a.act, img, r0 - 1, 6, a.H, W);
+        stage32(dzT, DS, W, 0, a.g, img, r0, 4, a.H, a.lw);
+        stage32(aT, AS, AP, 8, a.act, img, r0 - 1, 6, a.H, a.lw);
         __syncthreads();
-        for (int k = wave; k < 4 * cpr; k += 4) {
-            const int rl = k / cpr, px0 = (k % cpr) * 32;
-            uint4 A[2];
+        for (int k = 0; k < (4 << lcpr); ++k) {
+            const int rl = k >> lcpr, px0 = (k & ((1 << lcpr) - 1)) * 32;
+            const uint4 A = lds16(dzT + (16 * oh + n) * DS + rl * W + px0 + 8 * g);
 #pragma unroll
-            for (int oh = 0; oh < 2; ++oh) A[oh] = lds16(dzT + (16 * oh + n) * DS + rl * W + px0 + 8 * g);
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int ih = 0; ih < 2; ++ih) {
-                    const uint16_t *base = aT + (16 * ih + n) * AS + (rl + dy) * AP + 8 + px0 + 8 * g;
-                    const uint4 L = lds16(base - 8), M = lds16(base), R = lds16(base + 8);
-                    const uint4 Bx[3] = {funnel_l(L, M), M, funnel_r(M, R)};
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-                        for (int oh = 0; oh < 2; ++oh)
-                            acc[3 * dy + dx][oh][ih] = mma32(A[oh], Bx[dx], acc[3 * dy + dx][oh][ih]);
-                }
-#pragma unroll
-            for (int oh = 0; oh < 2; ++oh) accb[oh] = mma32(A[oh], ones, accb[oh]);
+            for (int dy = 0; dy < 3; ++dy) {
+                const uint16_t *base = aT + (16 * ih + n) * AS + (rl + dy) * AP + 8 + px0 + 8 * g;
+                const uint4 L = lds16(base - 8), M = lds16(base), R = lds16(base + 8);
+                acc[3 * dy + 0] = mma32(A, funnel_l(L, M), acc[3 * dy + 0]);
+                acc[3 * dy + 1] = mma32(A, M, acc[3 * dy + 1]);
+                acc[3 * dy + 2] = mma32(A, funnel_r(M, R), acc[3 * dy + 2]);
+            }
+            if (ih == 0) accb = mma32(A, ones, accb);
         }
-    }
-    __syncthreads();
-    float *red = reinterpret_cast<float *>(smem4);   // [9216 W2][32 b2], natural order
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
-#pragma unroll
-            for (int t = 0; t < 9; ++t)
-#pragma unroll
-                for (int oh = 0; oh < 2; ++oh)
-#pragma unroll
-                    for (int ih = 0; ih < 2; ++ih)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int o = slot_channel(16 * oh + 4 * g + i), ii = slot_channel(16 * ih + n);
-                            float &r = red[(o * 32 + ii) * 9 + t];
-                            r = (w ? r : 0.f) + acc[t][oh][ih][i];
-                        }
-            if (n == 0)
-#pragma unroll
-                for (int oh = 0; oh < 2; ++oh)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        float &r = red[9216 + slot_channel(16 * oh + 4 * g + i)];
-                        r = (w ? r : 0.f) + accb[oh][i];
-                    }
-        }
-        __syncthreads();
     }
     float *dst = a.part + int64_t(blockIdx.x) * kParams;
-    for (int e = tid; e < 9216; e += 256) dst[kOffW2 + e] = red[e];
-    if (tid < 32) dst[kOffB2 + tid] = red[9216 + tid];
+    const int ii = slot_channel(16 * ih + n);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int o = slot_channel(16 * oh + 4 * g + i);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) dst[kOffW2 + (o * 32 + ii) * 9 + t] = acc[t][i];
+        if (ih == 0 && n == 0) dst[kOffB2 + o] = accb[i];
+    }
 }
 
 // dW1[o][t] = sum_p dz1[o][p] xn[p + off_t] (B column t < 9), db1 (column 9 = ones)
@@ -467,9 +443,9 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
     for (int sb = 0; sb < 4; ++sb) {
         const int r0 = y0 + 4 * sb;
         __syncthreads();
-        stage32(dzT, DS, W, 0, a.g, img, r0, 4, a.H, W);
+        stage32(dzT, DS, W, 0, a.g, img, r0, 4, a.H, a.lw);
         for (int c = tid; c < 6 * W; c += 256) {
-            const int r = c / W, px = c % W, row = r0 - 1 + r;
+            const int r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
             uint16_t v = 0;
             if (row >= 0 && row < a.H)
                 v = bf16_bits(float(int(a.x[(int64_t(img) * a.H + row) * W + px]) - 128) * (1.f / 64.f));
@@ -528,9 +504,9 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     for (int sb = 0; sb < 4; ++sb) {
         const int r0 = y0 + 4 * sb;
         __syncthreads();
-        stage32(aT, DS, W, 0, a.act, img, r0, 4, a.H, W);
+        stage32(aT, DS, W, 0, a.act, img, r0, 4, a.H, a.lw);
         for (int c = tid; c < 6 * W; c += 256) {
-            const int r = c / W, px = c % W, row = r0 - 1 + r;
+            const int r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
             gT[r * AP + 8 + px] = (row >= 0 && row < a.H) ? a.g[(int64_t(img) * a.H + row) * W + px] : uint16_t(0);
         }
         __syncthreads();
@@ -956,7 +932,7 @@ WsLayout layout(int n, int H, int W) {
 
 size_t wgrad_lds(int W) {
     const size_t stage = size_t(32 * (4 * W + 8) + 32 * (6 * (W + 16) + 8)) * 2;
-    return std::max(stage, size_t(9216 + 32) * 4);
+    return std::max(stage, size_t(32 * 10) * 4);   // wgrad1 / wgrad3 reduce at most 320 floats
 }
 
 adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t *orig, int n, int H, int W,
@@ -998,6 +974,7 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     wa.part = part;
     wa.H = H;
     wa.W = W;
+    wa.lw = W == 64 ? 6 : 5;
     wa.bands = H / 16;
     const size_t lds = wgrad_lds(W);
     WgradArgs w3 = wa;
