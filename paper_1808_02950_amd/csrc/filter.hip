@@ -182,16 +182,22 @@ __device__ __forceinline__ bool wave_tile(const ConvArgs &a, WaveTile &t, int &g
 }
 
 template <int EPI>
-__device__ __forceinline__ void store32(const ConvArgs &a, int64_t pix, int g, const f32x4 d0, const f32x4 d1) {
+__device__ __forceinline__ uint4 load_mask(const ConvArgs &a, int64_t pix, int g) {
+    if constexpr (EPI == kMask) return *reinterpret_cast<const uint4 *>(a.mask + pix * 32 + 8 * g);
+    return uint4{0u, 0u, 0u, 0u};
+}
+
+// m: the mask activation of the same pixel (kMask), loaded ahead by the caller
+template <int EPI>
+__device__ __forceinline__ void store32(const ConvArgs &a, int64_t pix, int g, const f32x4 d0, const f32x4 d1,
+                                        const uint4 m) {
     uint4 v = {pack2(d0[0], d0[1]), pack2(d0[2], d0[3]), pack2(d1[0], d1[1]), pack2(d1[2], d1[3])};
-    const int64_t idx = pix * 32 + 8 * g;
     if constexpr (EPI == kRelu) {
         v = uint4{relu2(v.x), relu2(v.y), relu2(v.z), relu2(v.w)};
     } else {
-        const uint4 m = *reinterpret_cast<const uint4 *>(a.mask + idx);
         v = uint4{mask2(v.x, m.x), mask2(v.y, m.y), mask2(v.z, m.z), mask2(v.w, m.w)};
     }
-    *reinterpret_cast<uint4 *>(a.dst + idx) = v;
+    *reinterpret_cast<uint4 *>(a.dst + pix * 32 + 8 * g) = v;
 }
 
 __device__ __forceinline__ f32x4 bias4(const float *b, int base) {
@@ -209,9 +215,8 @@ __global__ __launch_bounds__(256) void k_conv1(const ConvArgs a) {
     const uint2 A1 = reinterpret_cast<const uint2 *>(a.w)[64 + lane];
     const f32x4 c0 = bias4(a.bias, 4 * g), c1 = bias4(a.bias, 16 + 4 * g);
     const int64_t plane = int64_t(T.img) * a.H * a.W;
-    for (int yy = 0; yy < 16; ++yy) {
-        const int y = T.y0 + yy;
-        uint16_t v[3];
+    // the 3x3 taps of row y for this lane's slots (g, j), zero outside the image
+    auto gather = [&](int y, uint16_t (&v)[3]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int sy = y + g - 1, sx = T.c0 + n + j - 1;
@@ -224,8 +229,16 @@ __global__ __launch_bounds__(256) void k_conv1(const ConvArgs a) {
                     v[j] = static_cast<const uint16_t *>(a.src)[q];
             }
         }
-        const uint2 B = {uint32_t(v[0]) | (uint32_t(v[1]) << 16), uint32_t(v[2])};
-        store32<EPI>(a, plane + int64_t(y) * a.W + T.c0 + n, g, mma16(A0, B, c0), mma16(A1, B, c1));
+    };
+    uint16_t nx[3];
+    gather(T.y0, nx);
+    for (int yy = 0; yy < 16; ++yy) {
+        const int y = T.y0 + yy;
+        const uint2 B = {uint32_t(nx[0]) | (uint32_t(nx[1]) << 16), uint32_t(nx[2])};
+        const int64_t pix = plane + int64_t(y) * a.W + T.c0 + n;
+        const uint4 m = load_mask<EPI>(a, pix, g);
+        if (yy + 1 < 16) gather(y + 1, nx);   // next row's loads overlap this row's work
+        store32<EPI>(a, pix, g, mma16(A0, B, c0), mma16(A1, B, c1), m);
     }
 }
 
@@ -242,28 +255,28 @@ __device__ __forceinline__ void load_row32(const ConvArgs &a, int64_t plane, int
     }
 }
 
+// B: input row y0 - 1 + s, loaded by the previous step; replaced by the next row
 template <int EPI, int P>
 __device__ __forceinline__ void conv32_step(const ConvArgs &a, const uint4 (&F)[9][2], const f32x4 (&bv)[2],
-                                            f32x4 (&acc)[3][2], int s, const WaveTile &T, int64_t plane, int n,
-                                            int g) {
-    uint4 B[3];
-    load_row32(a, plane, T.y0 - 1 + s, T.c0, n, g, B);
+                                            f32x4 (&acc)[3][2], uint4 (&B)[3], int s, const WaveTile &T,
+                                            int64_t plane, int n, int g) {
+    const uint4 Bc[3] = {B[0], B[1], B[2]};
+    const int64_t pix = plane + int64_t(T.y0 + s - 2) * a.W + T.c0 + n;
+    const uint4 m = s >= 2 ? load_mask<EPI>(a, pix, g) : uint4{0u, 0u, 0u, 0u};
+    if (s + 1 < 18) load_row32(a, plane, T.y0 + s, T.c0, n, g, B);
     // input row y0-1+s feeds output rows y0+s-dy; slot of output row y is (y - y0) mod 3
     constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        acc[S0][h] = mma32(F[0][h], B[0], bv[h]);
-        acc[S0][h] = mma32(F[1][h], B[1], acc[S0][h]);
-        acc[S0][h] = mma32(F[2][h], B[2], acc[S0][h]);
+        acc[S0][h] = mma32(F[0][h], Bc[0], bv[h]);
+        acc[S0][h] = mma32(F[1][h], Bc[1], acc[S0][h]);
+        acc[S0][h] = mma32(F[2][h], Bc[2], acc[S0][h]);
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) acc[S1][h] = mma32(F[3 + dx][h], B[dx], acc[S1][h]);
+        for (int dx = 0; dx < 3; ++dx) acc[S1][h] = mma32(F[3 + dx][h], Bc[dx], acc[S1][h]);
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) acc[S2][h] = mma32(F[6 + dx][h], B[dx], acc[S2][h]);
+        for (int dx = 0; dx < 3; ++dx) acc[S2][h] = mma32(F[6 + dx][h], Bc[dx], acc[S2][h]);
     }
-    if (s >= 2) {
-        const int y = T.y0 + s - 2;
-        store32<EPI>(a, plane + int64_t(y) * a.W + T.c0 + n, g, acc[S2][0], acc[S2][1]);
-    }
+    if (s >= 2) store32<EPI>(a, pix, g, acc[S2][0], acc[S2][1], m);
 }
 
 // 32 channels -> 32 channels
@@ -281,10 +294,12 @@ __global__ __launch_bounds__(256) void k_conv32(const ConvArgs a) {
     const f32x4 bv[2] = {bias4(a.bias, 4 * g), bias4(a.bias, 16 + 4 * g)};
     f32x4 acc[3][2] = {};
     const int64_t plane = int64_t(T.img) * a.H * a.W;
+    uint4 B[3];
+    load_row32(a, plane, T.y0 - 1, T.c0, n, g, B);
     for (int s = 0; s < 18; s += 3) {
-        conv32_step<EPI, 0>(a, F, bv, acc, s, T, plane, n, g);
-        conv32_step<EPI, 1>(a, F, bv, acc, s + 1, T, plane, n, g);
-        conv32_step<EPI, 2>(a, F, bv, acc, s + 2, T, plane, n, g);
+        conv32_step<EPI, 0>(a, F, bv, acc, B, s, T, plane, n, g);
+        conv32_step<EPI, 1>(a, F, bv, acc, B, s + 1, T, plane, n, g);
+        conv32_step<EPI, 2>(a, F, bv, acc, B, s + 2, T, plane, n, g);
     }
 }
 
@@ -304,16 +319,23 @@ __global__ __launch_bounds__(256) void k_conv_out(const ConvArgs a) {
     const int64_t plane = int64_t(T.img) * a.H * a.W;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     float lsum = 0.f, gsum = 0.f;
+    uint4 B[3];
+    load_row32(a, plane, T.y0 - 1, T.c0, n, g, B);
     for (int s = 0; s < 18; ++s) {
-        uint4 B[3];
-        load_row32(a, plane, T.y0 - 1 + s, T.c0, n, g, B);
-        acc = mma32(F[0], B[0], acc);
-        acc = mma32(F[1], B[1], acc);
-        acc = mma32(F[2], B[2], acc);
+        const uint4 Bc[3] = {B[0], B[1], B[2]};
+        const int64_t pix = plane + int64_t(T.y0 + s - 2) * a.W + T.c0 + n;
+        int xv = 0, ov = 0;
         if (s >= 2 && g == 0) {
-            const int64_t pix = plane + int64_t(T.y0 + s - 2) * a.W + T.c0 + n;
-            const float yv = float(int(a.x[pix]) - 128) * (1.f / 64.f) + (acc[2] + b3);
-            const float d = yv - float(int(a.orig[pix]) - 128) * (1.f / 64.f);
+            xv = a.x[pix];
+            ov = a.orig[pix];
+        }
+        if (s + 1 < 18) load_row32(a, plane, T.y0 + s, T.c0, n, g, B);
+        acc = mma32(F[0], Bc[0], acc);
+        acc = mma32(F[1], Bc[1], acc);
+        acc = mma32(F[2], Bc[2], acc);
+        if (s >= 2 && g == 0) {
+            const float yv = float(xv - 128) * (1.f / 64.f) + (acc[2] + b3);
+            const float d = yv - float(ov - 128) * (1.f / 64.f);
             const uint16_t gb = bf16_bits(d * a.gscale);
             a.dst[pix] = gb;
             if (a.y_out) a.y_out[pix] = yv;
