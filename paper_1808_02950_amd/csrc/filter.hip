@@ -22,8 +22,8 @@
 //
 // Three forms:
 //  * per-layer kernels (training): every layer and both input-gradient
-//    convolutions, one wave per 16-column strip of 16 rows; a 32-channel input
-//    row is loaded once and feeds the three output rows it touches;
+//    convolutions, one wave per 16-column strip of 4 rows; a 32-channel input
+//    row is loaded once (a step ahead) and feeds the three output rows it touches;
 //  * weight-gradient kernels: pixels are the contraction index, operands are
 //    transposed into LDS (channel-major) and the +-1 column shifts of the taps
 //    are funnel shifts of aligned 16-byte LDS reads;
@@ -153,6 +153,12 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ p, uint1
 
 enum Epi { kRelu = 0, kMask = 1 };
 
+// output rows per wave of the per-layer kernels: short tiles give several
+// waves per SIMD (the kernels wait on memory); the 32-channel kernels step
+// over kConvRows + 2 input rows in phases of three
+constexpr int kConvRows = 4;
+static_assert((kConvRows + 2) % 3 == 0, "phases of three");
+
 struct ConvArgs {
     const void *src;           // input: uint8 images, bf16 [n][H][W] or bf16 [n][H][W][32]
     const uint16_t *w;         // packed A operands
@@ -176,7 +182,7 @@ __device__ __forceinline__ bool wave_tile(const ConvArgs &a, WaveTile &t, int &g
     const int per = a.strips * a.chunks;
     t.img = gw / per;
     const int r = gw - t.img * per;
-    t.y0 = (r / a.strips) * 16;
+    t.y0 = (r / a.strips) * kConvRows;
     t.c0 = (r % a.strips) * 16;
     return true;
 }
@@ -232,12 +238,12 @@ __global__ __launch_bounds__(256) void k_conv1(const ConvArgs a) {
     };
     uint16_t nx[3];
     gather(T.y0, nx);
-    for (int yy = 0; yy < 16; ++yy) {
+    for (int yy = 0; yy < kConvRows; ++yy) {
         const int y = T.y0 + yy;
         const uint2 B = {uint32_t(nx[0]) | (uint32_t(nx[1]) << 16), uint32_t(nx[2])};
         const int64_t pix = plane + int64_t(y) * a.W + T.c0 + n;
         const uint4 m = load_mask<EPI>(a, pix, g);
-        if (yy + 1 < 16) gather(y + 1, nx);   // next row's loads overlap this row's work
+        if (yy + 1 < kConvRows) gather(y + 1, nx);   // next row's loads overlap this row's work
         store32<EPI>(a, pix, g, mma16(A0, B, c0), mma16(A1, B, c1), m);
     }
 }
@@ -263,7 +269,7 @@ __device__ __forceinline__ void conv32_step(const ConvArgs &a, const uint4 (&F)[
     const uint4 Bc[3] = {B[0], B[1], B[2]};
     const int64_t pix = plane + int64_t(T.y0 + s - 2) * a.W + T.c0 + n;
     const uint4 m = s >= 2 ? load_mask<EPI>(a, pix, g) : uint4{0u, 0u, 0u, 0u};
-    if (s + 1 < 18) load_row32(a, plane, T.y0 + s, T.c0, n, g, B);
+    if (s + 1 < kConvRows + 2) load_row32(a, plane, T.y0 + s, T.c0, n, g, B);
     // input row y0-1+s feeds output rows y0+s-dy; slot of output row y is (y - y0) mod 3
     constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3;
 #pragma unroll
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(256) void k_conv32(const ConvArgs a) {
     const int64_t plane = int64_t(T.img) * a.H * a.W;
     uint4 B[3];
     load_row32(a, plane, T.y0 - 1, T.c0, n, g, B);
-    for (int s = 0; s < 18; s += 3) {
+    for (int s = 0; s < kConvRows + 2; s += 3) {
         conv32_step<EPI, 0>(a, F, bv, acc, B, s, T, plane, n, g);
         conv32_step<EPI, 1>(a, F, bv, acc, B, s + 1, T, plane, n, g);
         conv32_step<EPI, 2>(a, F, bv, acc, B, s + 2, T, plane, n, g);
@@ -321,7 +327,7 @@ __global__ __launch_bounds__(256) void k_conv_out(const ConvArgs a) {
     float lsum = 0.f, gsum = 0.f;
     uint4 B[3];
     load_row32(a, plane, T.y0 - 1, T.c0, n, g, B);
-    for (int s = 0; s < 18; ++s) {
+    for (int s = 0; s < kConvRows + 2; ++s) {
         const uint4 Bc[3] = {B[0], B[1], B[2]};
         const int64_t pix = plane + int64_t(T.y0 + s - 2) * a.W + T.c0 + n;
         int xv = 0, ov = 0;
@@ -329,7 +335,7 @@ __global__ __launch_bounds__(256) void k_conv_out(const ConvArgs a) {
             xv = a.x[pix];
             ov = a.orig[pix];
         }
-        if (s + 1 < 18) load_row32(a, plane, T.y0 + s, T.c0, n, g, B);
+        if (s + 1 < kConvRows + 2) load_row32(a, plane, T.y0 + s, T.c0, n, g, B);
         acc = mma32(F[0], Bc[0], acc);
         acc = mma32(F[1], Bc[1], acc);
         acc = mma32(F[2], Bc[2], acc);
@@ -563,16 +569,36 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     for (int e = tid; e < 288; e += 256) dst[kOffW3 + e] = red[e];
 }
 
-// fixed-order sums over workgroups: deterministic gradient and loss.  A block
-// takes 16 consecutive parameters; its 16 row groups each sum every 16th
-// partial row (all loads of a thread in flight together), and the 16 group
-// sums are added in a fixed order.
+// fixed-order sums over workgroups: deterministic gradient and loss.  Blocks
+// below kRedParamBlocks take 16 consecutive weight-gradient entries; their 16
+// row groups each sum every 16th partial row (all loads of a thread in flight
+// together) and the group sums are added in a fixed order.  The last two
+// blocks sum the per-wave partials of the loss-gradient kernel (b3's gradient,
+// then the loss) with all 256 threads and a fixed-order tree.
 constexpr int kRedCols = 16, kRedGroups = 16;
+constexpr int kRedParamBlocks = (kOffB3 + kRedCols - 1) / kRedCols;
 __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, int n_wg,
                                                 const float *__restrict__ part3, int n_w3, float inv_count,
                                                 float *__restrict__ grad, float *__restrict__ loss) {
-    __shared__ float sm[kRedGroups][kRedCols];
-    const int c = threadIdx.x % kRedCols, q = threadIdx.x / kRedCols;
+    __shared__ float sm[256];
+    const int tid = threadIdx.x;
+    if (int(blockIdx.x) >= kRedParamBlocks) {
+        const int k = int(blockIdx.x) == kRedParamBlocks ? 1 : 0;   // 1: b3 gradient, 0: loss
+        float s = 0.f;
+        for (int w = tid; w < n_w3; w += 256) s += part3[2 * w + k];
+        sm[tid] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) sm[tid] += sm[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (k) grad[kOffB3] = sm[0];
+            else if (loss) *loss = sm[0] * inv_count;
+        }
+        return;
+    }
+    const int c = tid % kRedCols, q = tid / kRedCols;
     const int p = int(blockIdx.x) * kRedCols + c;
     float s = 0.f;
     if (p < kOffB3) {
@@ -585,18 +611,14 @@ __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, 
             for (int k = 0; k < 16; ++k) s += v[k];
         }
         for (; w < n_wg; w += kRedGroups) s += part[int64_t(w) * kParams + p];
-    } else if (p == kOffB3 || p == kParams) {
-        const int k = p == kOffB3 ? 1 : 0;
-        for (int w = q; w < n_w3; w += kRedGroups) s += part3[2 * w + k];
     }
-    sm[q][c] = s;
+    sm[tid] = s;
     __syncthreads();
-    if (q == 0) {
+    if (q == 0 && p < kOffB3) {
         float t = 0.f;
 #pragma unroll
-        for (int k = 0; k < kRedGroups; ++k) t += sm[k][c];
-        if (p < kParams) grad[p] = t;
-        else if (p == kParams && loss) *loss = t * inv_count;
+        for (int k = 0; k < kRedGroups; ++k) t += sm[k * kRedCols + c];
+        grad[p] = t;
     }
 }
 
@@ -937,7 +959,7 @@ WsLayout layout(int n, int H, int W) {
     WsLayout L;
     const int64_t px = int64_t(n) * H * W;
     L.n_wg = n * (H / 16);
-    L.n_w3 = n * (W / 16) * (H / 16);
+    L.n_w3 = n * (W / 16) * (H / kConvRows);
     int64_t o = 0;
     L.packed = o; o += up256(kPackBytes);
     L.a1 = o; o += up256(px * 64);
@@ -972,7 +994,7 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     c.H = H;
     c.W = W;
     c.strips = W / 16;
-    c.chunks = H / 16;
+    c.chunks = H / kConvRows;
     c.total = n * c.strips * c.chunks;
     const dim3 grid((c.total + 3) / 4), blk(256);
     ConvArgs c1 = c;   // layer 1
@@ -1008,7 +1030,7 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     WgradArgs w1 = wa;
     w1.g = dz1; w1.x = recon;
     hipLaunchKernelGGL(k_wgrad1, dim3(L.n_wg), blk, lds, s, w1);
-    hipLaunchKernelGGL(k_reduce, dim3((kParams + 1 + kRedCols - 1) / kRedCols), blk, 0, s, part, L.n_wg, part3, L.n_w3,
+    hipLaunchKernelGGL(k_reduce, dim3(kRedParamBlocks + 2), blk, 0, s, part, L.n_wg, part3, L.n_w3,
                        float(1.0 / (double(n) * H * W)), grad, loss);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
