@@ -452,15 +452,19 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
 }
 
 // dW1[o][t] = sum_p dz1[o][p] xn[p + off_t] (B column t < 9), db1 (column 9 = ones)
+// The single-channel tiles are small, so wgrad1 and wgrad3 stage 8 rows at a
+// time (two staging rounds per band instead of four).
+constexpr int kSb1 = 8;
+
 __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
     extern __shared__ uint4 smem4[];
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
-    const int W = a.W, DS = dz_stride(W), AP = act_pitch(W);
+    const int W = a.W, DS = kSb1 * W + 8, AP = act_pitch(W);
     uint16_t *dzT = sm, *xT = sm + 32 * DS;
     const int img = int(blockIdx.x) / a.bands, y0 = (int(blockIdx.x) % a.bands) * 16;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int c = tid; c < 6 * 16; c += 256) {
+    for (int c = tid; c < (kSb1 + 2) * 16; c += 256) {
         const int k = c & 15, r = c >> 4;
         xT[r * AP + (k < 8 ? k : W + k)] = 0;
     }
@@ -468,11 +472,11 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
     const int tap = n < 9 ? n : 4;
     const int dy = tap / 3, dx = tap % 3;
     const int cpr = W / 32;
-    for (int sb = 0; sb < 4; ++sb) {
-        const int r0 = y0 + 4 * sb;
+    for (int sb = 0; sb < 16 / kSb1; ++sb) {
+        const int r0 = y0 + kSb1 * sb;
         __syncthreads();
-        stage32(dzT, DS, W, 0, a.g, img, r0, 4, a.H, a.lw);
-        for (int c = tid; c < 6 * W; c += 256) {
+        stage32(dzT, DS, W, 0, a.g, img, r0, kSb1, a.H, a.lw);
+        for (int c = tid; c < (kSb1 + 2) * W; c += 256) {
             const int r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
             uint16_t v = 0;
             if (row >= 0 && row < a.H)
@@ -480,7 +484,7 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
             xT[r * AP + 8 + px] = v;
         }
         __syncthreads();
-        for (int k = wave; k < 4 * cpr; k += 4) {
+        for (int k = wave; k < kSb1 * cpr; k += 4) {
             const int rl = k / cpr, px0 = (k % cpr) * 32;
             const uint16_t *base = xT + (rl + dy) * AP + 8 + px0 + 8 * g;
             const uint4 L = lds16(base - 8), M = lds16(base), R = lds16(base + 8);
@@ -516,12 +520,12 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
 __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     extern __shared__ uint4 smem4[];
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
-    const int W = a.W, DS = dz_stride(W), AP = act_pitch(W);
+    const int W = a.W, DS = kSb1 * W + 8, AP = act_pitch(W);
     uint16_t *aT = sm, *gT = sm + 32 * DS;
     const int img = int(blockIdx.x) / a.bands, y0 = (int(blockIdx.x) % a.bands) * 16;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int c = tid; c < 6 * 16; c += 256) {
+    for (int c = tid; c < (kSb1 + 2) * 16; c += 256) {
         const int k = c & 15, r = c >> 4;
         gT[r * AP + (k < 8 ? k : W + k)] = 0;
     }
@@ -529,16 +533,16 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     const int tap = n < 9 ? n : 4;
     const int dy = tap / 3, dx = tap % 3;
     const int cpr = W / 32;
-    for (int sb = 0; sb < 4; ++sb) {
-        const int r0 = y0 + 4 * sb;
+    for (int sb = 0; sb < 16 / kSb1; ++sb) {
+        const int r0 = y0 + kSb1 * sb;
         __syncthreads();
-        stage32(aT, DS, W, 0, a.act, img, r0, 4, a.H, a.lw);
-        for (int c = tid; c < 6 * W; c += 256) {
+        stage32(aT, DS, W, 0, a.act, img, r0, kSb1, a.H, a.lw);
+        for (int c = tid; c < (kSb1 + 2) * W; c += 256) {
             const int r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
             gT[r * AP + 8 + px] = (row >= 0 && row < a.H) ? a.g[(int64_t(img) * a.H + row) * W + px] : uint16_t(0);
         }
         __syncthreads();
-        for (int k = wave; k < 4 * cpr; k += 4) {
+        for (int k = wave; k < kSb1 * cpr; k += 4) {
             const int rl = k / cpr, px0 = (k % cpr) * 32;
             const uint16_t *base = gT + (rl + 2 - dy) * AP + 8 + px0 + 8 * g;
             const uint4 L = lds16(base - 8), M = lds16(base), R = lds16(base + 8);
@@ -975,8 +979,9 @@ WsLayout layout(int n, int H, int W) {
 }
 
 size_t wgrad_lds(int W) {
-    const size_t stage = size_t(32 * (4 * W + 8) + 32 * (6 * (W + 16) + 8)) * 2;
-    return std::max(stage, size_t(32 * 10) * 4);   // wgrad1 / wgrad3 reduce at most 320 floats
+    const size_t stage2 = size_t(32 * (4 * W + 8) + 32 * (6 * (W + 16) + 8)) * 2;        // wgrad2
+    const size_t stage13 = size_t(32 * (kSb1 * W + 8) + (kSb1 + 2) * (W + 16)) * 2;      // wgrad1, wgrad3
+    return std::max(std::max(stage2, stage13), size_t(32 * 10) * 4);
 }
 
 adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t *orig, int n, int H, int W,
