@@ -288,6 +288,10 @@ __device__ __forceinline__ void conv32_step(const ConvArgs &a, const uint4 (&F)[
 // 32 channels -> 32 channels
 template <int EPI>
 __global__ __launch_bounds__(256) void k_conv32(const ConvArgs a) {
+    // the 18 KB of packed weights are read from memory once per workgroup
+    __shared__ uint4 sw[9 * 2 * 64];
+    for (int i = threadIdx.x; i < 9 * 2 * 64; i += 256) sw[i] = reinterpret_cast<const uint4 *>(a.w)[i];
+    __syncthreads();
     WaveTile T;
     int gw;
     if (!wave_tile(a, T, gw)) return;
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(256) void k_conv32(const ConvArgs a) {
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) F[t][h] = reinterpret_cast<const uint4 *>(a.w)[(t * 2 + h) * 64 + lane];
+        for (int h = 0; h < 2; ++h) F[t][h] = sw[(t * 2 + h) * 64 + lane];
     const f32x4 bv[2] = {bias4(a.bias, 4 * g), bias4(a.bias, 16 + 4 * g)};
     f32x4 acc[3][2] = {};
     const int64_t plane = int64_t(T.img) * a.H * a.W;
@@ -394,6 +398,48 @@ __device__ __forceinline__ void stage32(uint16_t *T, int sstride, int rpitch, in
     }
 }
 
+// The same in two phases, so the global loads of the next rows can be in
+// flight while the current ones are used: load into registers (at most MAXC
+// 16-byte chunks per thread), later transpose them into LDS.
+template <int MAXC>
+struct Staged {
+    uint4 v[MAXC];
+};
+template <int MAXC>
+__device__ __forceinline__ void stage_load(Staged<MAXC> &st, const uint16_t *src, int img, int row0, int nrows,
+                                           int H, int lw) {
+    const int W = 1 << lw;
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k) {
+        const int c = int(threadIdx.x) + 256 * k;
+        st.v[k] = uint4{0u, 0u, 0u, 0u};
+        if (c < (nrows * 4) << lw) {
+            const int px = c & (W - 1), rest = c >> lw, q = rest & 3, row = row0 + (rest >> 2);
+            if (row >= 0 && row < H)
+                st.v[k] = *reinterpret_cast<const uint4 *>(src + ((int64_t(img) * H + row) * W + px) * 32 + 8 * q);
+        }
+    }
+}
+template <int MAXC>
+__device__ __forceinline__ void stage_store(const Staged<MAXC> &st, uint16_t *T, int sstride, int rpitch, int coff,
+                                            int nrows, int lw) {
+    const int W = 1 << lw;
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k) {
+        const int c = int(threadIdx.x) + 256 * k;
+        if (c < (nrows * 4) << lw) {
+            const int px = c & (W - 1), rest = c >> lw, q = rest & 3, r = rest >> 2;
+            uint16_t *d = T + (8 * q) * sstride + r * rpitch + coff + px;
+            const uint32_t w[4] = {st.v[k].x, st.v[k].y, st.v[k].z, st.v[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                d[(2 * j) * sstride] = uint16_t(w[j] & 0xffffu);
+                d[(2 * j + 1) * sstride] = uint16_t(w[j] >> 16);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ int dz_stride(int W) { return 4 * W + 8; }
 __device__ __forceinline__ int act_pitch(int W) { return W + 16; }
 __device__ __forceinline__ int act_stride(int W) { return 6 * (W + 16) + 8; }
@@ -420,12 +466,20 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     f32x4 accb = {0.f, 0.f, 0.f, 0.f};
     const uint4 ones = {kOne2, kOne2, kOne2, kOne2};
     const int lcpr = a.lw - 5;   // log2 of the 32-pixel chunks per row
+    // sub-band sb + 1 is loaded into registers while sub-band sb is computed
+    Staged<4> sd;   // 4 rows x 4 chunks x W <= 1024 chunks
+    Staged<6> sa;   // 6 rows
+    stage_load(sd, a.g, img, y0, 4, a.H, a.lw);
+    stage_load(sa, a.act, img, y0 - 1, 6, a.H, a.lw);
     for (int sb = 0; sb < 4; ++sb) {
-        const int r0 = y0 + 4 * sb;
         __syncthreads();
-        stage32(dzT, DS, W, 0, a.g, img, r0, 4, a.H, a.lw);
-        stage32(aT, AS, AP, 8, a.act, img, r0 - 1, 6, a.H, a.lw);
+        stage_store(sd, dzT, DS, W, 0, 4, a.lw);
+        stage_store(sa, aT, AS, AP, 8, 6, a.lw);
         __syncthreads();
+        if (sb + 1 < 4) {
+            stage_load(sd, a.g, img, y0 + 4 * (sb + 1), 4, a.H, a.lw);
+            stage_load(sa, a.act, img, y0 + 4 * (sb + 1) - 1, 6, a.H, a.lw);
+        }
         for (int k = 0; k < (4 << lcpr); ++k) {
             const int rl = k >> lcpr, px0 = (k & ((1 << lcpr) - 1)) * 32;
             const uint4 A = lds16(dzT + (16 * oh + n) * DS + rl * W + px0 + 8 * g);
