@@ -526,18 +526,33 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
     const int tap = n < 9 ? n : 4;
     const int dy = tap / 3, dx = tap % 3;
     const int cpr = W / 32;
+    // the next sub-band is loaded into registers while the current one is used
+    Staged<kSb1> sd;
+    uint16_t xv[3];   // (kSb1 + 2) rows x W <= 640 values, 3 per thread
+    auto load_x = [&](int r0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int c = tid + 256 * k, r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
+            xv[k] = 0;
+            if (c < (kSb1 + 2) * W && row >= 0 && row < a.H)
+                xv[k] = bf16_bits(float(int(a.x[(int64_t(img) * a.H + row) * W + px]) - 128) * (1.f / 64.f));
+        }
+    };
+    stage_load(sd, a.g, img, y0, kSb1, a.H, a.lw);
+    load_x(y0);
     for (int sb = 0; sb < 16 / kSb1; ++sb) {
-        const int r0 = y0 + kSb1 * sb;
         __syncthreads();
-        stage32(dzT, DS, W, 0, a.g, img, r0, kSb1, a.H, a.lw);
-        for (int c = tid; c < (kSb1 + 2) * W; c += 256) {
-            const int r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
-            uint16_t v = 0;
-            if (row >= 0 && row < a.H)
-                v = bf16_bits(float(int(a.x[(int64_t(img) * a.H + row) * W + px]) - 128) * (1.f / 64.f));
-            xT[r * AP + 8 + px] = v;
+        stage_store(sd, dzT, DS, W, 0, kSb1, a.lw);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int c = tid + 256 * k;
+            if (c < (kSb1 + 2) * W) xT[(c >> a.lw) * AP + 8 + (c & (W - 1))] = xv[k];
         }
         __syncthreads();
+        if (sb + 1 < 16 / kSb1) {
+            stage_load(sd, a.g, img, y0 + kSb1 * (sb + 1), kSb1, a.H, a.lw);
+            load_x(y0 + kSb1 * (sb + 1));
+        }
         for (int k = wave; k < kSb1 * cpr; k += 4) {
             const int rl = k / cpr, px0 = (k % cpr) * 32;
             const uint16_t *base = xT + (rl + dy) * AP + 8 + px0 + 8 * g;
@@ -587,15 +602,31 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     const int tap = n < 9 ? n : 4;
     const int dy = tap / 3, dx = tap % 3;
     const int cpr = W / 32;
+    Staged<kSb1> sa;
+    uint16_t gv[3];
+    auto load_g = [&](int r0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int c = tid + 256 * k, r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
+            gv[k] = 0;
+            if (c < (kSb1 + 2) * W && row >= 0 && row < a.H) gv[k] = a.g[(int64_t(img) * a.H + row) * W + px];
+        }
+    };
+    stage_load(sa, a.act, img, y0, kSb1, a.H, a.lw);
+    load_g(y0);
     for (int sb = 0; sb < 16 / kSb1; ++sb) {
-        const int r0 = y0 + kSb1 * sb;
         __syncthreads();
-        stage32(aT, DS, W, 0, a.act, img, r0, kSb1, a.H, a.lw);
-        for (int c = tid; c < (kSb1 + 2) * W; c += 256) {
-            const int r = c >> a.lw, px = c & (W - 1), row = r0 - 1 + r;
-            gT[r * AP + 8 + px] = (row >= 0 && row < a.H) ? a.g[(int64_t(img) * a.H + row) * W + px] : uint16_t(0);
+        stage_store(sa, aT, DS, W, 0, kSb1, a.lw);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int c = tid + 256 * k;
+            if (c < (kSb1 + 2) * W) gT[(c >> a.lw) * AP + 8 + (c & (W - 1))] = gv[k];
         }
         __syncthreads();
+        if (sb + 1 < 16 / kSb1) {
+            stage_load(sa, a.act, img, y0 + kSb1 * (sb + 1), kSb1, a.H, a.lw);
+            load_g(y0 + kSb1 * (sb + 1));
+        }
         for (int k = wave; k < kSb1 * cpr; k += 4) {
             const int rl = k / cpr, px0 = (k % cpr) * 32;
             const uint16_t *base = gT + (rl + 2 - dy) * AP + 8 + px0 + 8 * g;
