@@ -126,7 +126,18 @@ struct Tf {
         for (int k = 0; k < 8; ++k) l = std::lcm(l, n(k));
         return l;
     }
-    static constexpr int32_t c(int k) { return L1() / n(k); }
+    // c_k = L1 / n_k as a table, so that a use with an unrolled index folds to a
+    // constant instead of running the lcm loops on the device
+    struct CTab {
+        int32_t c[8];
+    };
+    static constexpr CTab make_c() {
+        CTab t{};
+        for (int k = 0; k < 8; ++k) t.c[k] = L1() / n(k);
+        return t;
+    }
+    static constexpr CTab kC = make_c();
+    static constexpr int32_t c(int k) { return kC.c[k]; }
     struct Tables {
         int32_t mu[64];   // mu with mu^2 = n_k n_l, or 0 when n_k n_l is not a square
         double skl[64];   // s_k s_l = 1 / sqrt(n_k n_l)

@@ -1,6 +1,7 @@
 // Batched evaluation: many images of uneven sizes x several transforms x every
-// retention level r in one persistent launch (the rate-distortion sweep of
-// Sec. 6.1.1, where the paper averages MSE / PSNR over images for each r).
+// retention level r in one persistent launch per arithmetic (the rate-distortion
+// sweep of Sec. 6.1.1, where the paper averages MSE / PSNR over images for each
+// r).
 //
 // A work item is one tile of 64 blocks of one image and a group of transforms;
 // one wave owns an item, one lane owns one block.  Per transform the lane
@@ -8,10 +9,15 @@
 // order, lane-interleaved so every read is conflict-free), then walks the
 // zig-zag scan: step j adds coefficient j's outer product to the block's
 // reconstruction numerator, rounds, clips and scores it, giving the squared
-// error for r = j + 1.  Integer transforms accumulate exact integer numerators
-// over L = lcm(n)^2 (bit-exact against the oracle); the exact DCT accumulates in
-// float64.  Each step's per-lane errors are summed across the wave and added to
-// the [image][transform][r] table.
+// error for r = j + 1.  Each step's per-lane errors are summed across the wave
+// and added to the [image][transform][r] table.
+//
+// Integer transforms accumulate exact integer numerators over L = lcm(n)^2
+// (bit-exact against the oracle).  Their coefficients are staged as int16 (8 KB
+// per wave), so many waves share a compute unit and hide each other's latency.
+// The exact DCT accumulates in float64 and stages float64 coefficients (32 KB per
+// wave); it runs as a second kernel so that its LDS footprint does not cap the
+// occupancy of the integer sweep.
 #include <math.h>
 #include <string.h>
 
@@ -42,9 +48,12 @@ struct BatchArgs {
     int32_t n_images;
     int32_t n_transforms;
     int32_t r_lo, r_hi;
-    int32_t split;                    // transform groups per tile
+    int32_t split;                    // integer-transform groups per tile
     int32_t total_tiles;
     int32_t tids[kMaxBatchTransforms];
+    int32_t n_int, n_dct;             // integer / DCT entries of the list
+    int32_t int_pos[kMaxBatchTransforms];   // their positions in the list
+    int32_t dct_pos[kMaxBatchTransforms];
     BatchImg img[kMaxBatchImages];
 };
 
@@ -150,112 +159,235 @@ __device__ __forceinline__ void fwd_full(const int (&x)[8], int (&y)[8]) {
     }
 }
 
-// Per-wave coefficient staging: 64 coefficients x 64 lanes, entry [z][lane]
-// (float64 for the DCT, int32 for integer transforms).  Single-wave
-// workgroups, so each wave owns the whole array.
-__shared__ double g_stage[64 * 64];
+// ---------------------------------------------------------------- integer sweep
+//
+// Step j of the scan adds the coefficient at zig-zag position j, (k, l):
+//     A[x][y] += V(k,l) T[k][x] T[l][y],   V = Y c_k c_l,  Y = T A T^T.
+// With g_k the gcd of row k's entries, Y' = Y / (g_k g_l) fits int16 for 8-bit
+// input, and the step becomes two 24-bit products per entry:
+//     u[x] = Y' T[k][x],   A[x][y] += u[x] w_y,   w_y = g_k g_l c_k c_l T[l][y].
+// The sixteen wave-uniform factors of a step sit in one table row (one scalar
+// load), so the step has no branches.
 
-// A[:, Y] += t u for a wave-uniform t in {0, +-1, +-2}
-template <int Y>
-__device__ __forceinline__ void add_col(int (&A)[8][8], const int (&u)[8], int t) {
-    if (t == 1) {
-#pragma unroll
-        for (int x = 0; x < 8; ++x) A[x][Y] += u[x];
-    } else if (t == -1) {
-#pragma unroll
-        for (int x = 0; x < 8; ++x) A[x][Y] -= u[x];
-    } else if (t == 2) {
-#pragma unroll
-        for (int x = 0; x < 8; ++x) A[x][Y] += u[x] + u[x];
-    } else if (t == -2) {
-#pragma unroll
-        for (int x = 0; x < 8; ++x) A[x][Y] -= u[x] + u[x];
+struct StepEnt {
+    int16_t w[8];     // g_k g_l c_k c_l T[l][y]
+    int16_t tk[8];    // T[k][x]
+};
+struct StepTab {
+    StepEnt s[64];
+};
+
+template <int ID>
+constexpr int32_t row_gcd(int k) {
+    int32_t g = 0;
+    for (int m = 0; m < 8; ++m) {
+        int32_t v = Tf<ID>::t(k, m) < 0 ? -Tf<ID>::t(k, m) : Tf<ID>::t(k, m);
+        int32_t a = g;
+        while (v) {
+            const int32_t r = a % v;
+            a = v;
+            v = r;
+        }
+        g = a;
     }
+    return g;
 }
 
-template <size_t... Ys>
-__device__ __forceinline__ void add_outer(int (&A)[8][8], const int (&u)[8], const int8_t (&row)[8],
-                                          std::index_sequence<Ys...>) {
-    (add_col<int(Ys)>(A, u, int(row[Ys])), ...);
+constexpr int32_t log2_exact(int32_t v) {
+    int32_t s = 0;
+    while ((1 << s) < v) ++s;
+    return (1 << s) == v ? s : -1;
 }
+
+template <int ID>
+constexpr StepTab make_steps() {
+    StepTab t{};
+    for (int j = 0; j < 64; ++j) {
+        const int k = kZZ[j] >> 3, l = kZZ[j] & 7;
+        const int32_t g = row_gcd<ID>(k) * row_gcd<ID>(l);
+        for (int x = 0; x < 8; ++x) {
+            t.s[j].tk[x] = int16_t(Tf<ID>::t(k, x));
+            t.s[j].w[x] = int16_t(g * Tf<ID>::c(k) * Tf<ID>::c(l) * Tf<ID>::t(l, x));
+        }
+    }
+    return t;
+}
+
+// log2 of each row's gcd (a power of two for every built-in transform)
+template <int ID>
+struct RowShift {
+    struct Tab {
+        int32_t sh[8];
+    };
+    static constexpr Tab make() {
+        Tab t{};
+        for (int k = 0; k < 8; ++k) t.sh[k] = log2_exact(row_gcd<ID>(k));
+        return t;
+    }
+    static constexpr Tab kT = make();
+};
+
+// Range facts the integer sweep relies on, checked at compile time:
+//  * |Y'| <= 32767: the largest |Y(k,l)| over 8-bit blocks is 255 times the
+//    larger of the positive and negative parts of the outer product of rows k, l;
+//  * u fits signed 24 bits, w signed 16 bits, and |u w| < 2^31;
+//  * 2L fits signed 24 bits (the tie test multiplies it by the quotient).
+// The numerator itself stays below 2040 L in magnitude: every prefix of the scan
+// is an orthogonal projection of the block, whose norm is at most 255 * 8.
+template <int ID>
+constexpr bool int_sweep_ranges_ok() {
+    int64_t umax = 0, wmax = 0;
+    for (int k = 0; k < 8; ++k)
+        for (int l = 0; l < 8; ++l) {
+            int64_t pos = 0, neg = 0;
+            for (int x = 0; x < 8; ++x)
+                for (int y = 0; y < 8; ++y) {
+                    const int64_t p = int64_t(Tf<ID>::t(k, x)) * Tf<ID>::t(l, y);
+                    if (p > 0) pos += p; else neg -= p;
+                }
+            const int64_t g = int64_t(row_gcd<ID>(k)) * row_gcd<ID>(l);
+            if (log2_exact(int32_t(g)) < 0) return false;
+            const int64_t ymax = 255 * (pos > neg ? pos : neg) / g;
+            if (ymax > 32767) return false;
+            for (int x = 0; x < 8; ++x) {
+                const int64_t tk = Tf<ID>::t(k, x) < 0 ? -Tf<ID>::t(k, x) : Tf<ID>::t(k, x);
+                const int64_t tl = Tf<ID>::t(l, x) < 0 ? -Tf<ID>::t(l, x) : Tf<ID>::t(l, x);
+                umax = umax > ymax * tk ? umax : ymax * tk;
+                const int64_t w = g * Tf<ID>::c(k) * Tf<ID>::c(l) * tl;
+                wmax = wmax > w ? wmax : w;
+            }
+        }
+    const int64_t L = Tf<ID>::L();
+    return umax < (1 << 23) && wmax < (1 << 15) && umax * wmax < (int64_t(1) << 31) &&
+           2 * L < (1 << 23) && int64_t(2040) * L * 2 + L < (int64_t(1) << 31);
+}
+
+__device__ constexpr StepTab kStepDev[7] = {make_steps<ADCT_T1>(), make_steps<ADCT_T1>(),
+                                            make_steps<ADCT_T2>(), make_steps<ADCT_LO>(),
+                                            make_steps<ADCT_T6>(), make_steps<ADCT_RDCT>(),
+                                            make_steps<ADCT_T4>()};
+static_assert(int_sweep_ranges_ok<ADCT_T1>() && int_sweep_ranges_ok<ADCT_T2>() &&
+                  int_sweep_ranges_ok<ADCT_LO>() && int_sweep_ranges_ok<ADCT_T6>() &&
+                  int_sweep_ranges_ok<ADCT_RDCT>() && int_sweep_ranges_ok<ADCT_T4>(),
+              "integer sweep ranges");
+
+// Exact round-half-to-even(n / L) clipped to [0, 255] without a 32-bit
+// multiply.  With c = clip(n) and u = 2c + L, the half-up quotient is
+// q = floor(u / 2L), found in float:
+//  * small L: u / 2L = c / L + 1/2 and fma(c, 1/L, 1/2 + 1/(4L)) lies in
+//    [q, q + 1): the fractions of u / 2L are multiples of 1/(2L), and the
+//    rounding error (below 256 * 2^-23 + 2^-24) is under the 1/(4L) offset;
+//  * large L: write 2L = 2^a b with b odd; q = floor(v / b) for
+//    v = u >> a = (c + L/2) >> (a - 1), and fma(v, 1/b, 1/(2b)) lies in
+//    [q, q + 1) by the same argument with spacing 1/b.
+// At a tie u = 2L q, i.e. c + L/2 - L q = 0 (L is even); that remainder is an
+// integer in [0, L), so minus one it is negative exactly at a tie, where an odd
+// q loses its low bit.
+template <int ID>
+struct IntRound {
+    static constexpr int32_t L = Tf<ID>::L();
+    static constexpr bool kShift = L >= 4096;
+    static constexpr int32_t a() {
+        int32_t s = 0;
+        while (((2 * L) >> s & 1) == 0) ++s;
+        return s;
+    }
+    static constexpr int32_t kA = kShift ? a() : 0;
+    static constexpr int32_t kB = (2 * L) >> kA;           // odd part of 2L (large L)
+    static_assert(!kShift || (kA >= 1 && kB <= 8192), "divisor too large for the float quotient");
+    static_assert(kShift || L <= 8192, "small-L path needs 1/(4L) above the rounding error");
+    static_assert(int64_t(256) * L < (int64_t(1) << (24 + kA)), "quotient input must be exact in float");
+    static_assert(L % 2 == 0, "the tie test halves u");
+};
+
+// wave-uniform constants of the rounding, held in scalar registers (a VOP3
+// instruction takes no 32-bit literal on this target)
+struct IntRoundRegs {
+    int32_t hLm1, mL;     // L/2 - 1, -L
+};
+
+template <int ID>
+__device__ __forceinline__ IntRoundRegs int_round_regs() {
+    IntRoundRegs r;
+    asm("s_mov_b32 %0, %1" : "=s"(r.hLm1) : "i"(IntRound<ID>::L / 2 - 1));
+    asm("s_mov_b32 %0, %1" : "=s"(r.mL) : "i"(-IntRound<ID>::L));
+    return r;
+}
+
+template <int ID>
+__device__ __forceinline__ int rne_clip_int(int n, const IntRoundRegs &c) {
+    using R = IntRound<ID>;
+    const int nc = min(max(n, 0), 255 * R::L);
+    float f;
+    if constexpr (R::kShift) {
+        constexpr float kInv = 1.0f / float(R::kB);
+        constexpr float kOff = 0.5f / float(R::kB);
+        f = __builtin_fmaf(float(uint32_t(nc + R::L / 2) >> (R::kA - 1)), kInv, kOff);
+    } else {
+        constexpr float kInv = 1.0f / float(R::L);
+        constexpr float kOff = 0.5f + 0.25f / float(R::L);
+        f = __builtin_fmaf(float(nc), kInv, kOff);
+    }
+    const uint32_t q = uint32_t(f);
+    const uint32_t tie = uint32_t(nc + c.hLm1 + __mul24(int(q), c.mL)) >> 31;
+    return int(q & ~tie);
+}
+
+// Per-wave coefficient staging for the integer sweep: [z][lane] int16.
+__shared__ int16_t g_stage16[64 * 64];
 
 // column pass of the forward for column Lc: Y[:, Lc] = T Z[:, Lc]; stores
-// V = Y c_k c_l at the coefficient's zig-zag slot
+// Y' = Y / (g_k g_Lc) at the coefficient's zig-zag slot
 template <int ID, int Lc>
-__device__ __forceinline__ void fwd_col(const int (&Z)[8][8], int *lds, int lane) {
+__device__ __forceinline__ void fwd_col16(const int (&Z)[8][8], int16_t *lds, int lane) {
     int in[8], out[8];
 #pragma unroll
     for (int x = 0; x < 8; ++x) in[x] = Z[x][Lc];
     fwd_full<ID>(in, out);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        lds[zz_pos(k, Lc) * 64 + lane] = out[k] * (Tf<ID>::c(k) * Tf<ID>::c(Lc));
+        lds[zz_pos(k, Lc) * 64 + lane] = int16_t(out[k] >> (RowShift<ID>::kT.sh[k] + RowShift<ID>::kT.sh[Lc]));
 }
 
 template <int ID, size_t... Ls>
-__device__ __forceinline__ void fwd_cols(const int (&Z)[8][8], int *lds, int lane, std::index_sequence<Ls...>) {
-    (fwd_col<ID, int(Ls)>(Z, lds, lane), ...);
+__device__ __forceinline__ void fwd_cols16(const int (&Z)[8][8], int16_t *lds, int lane, std::index_sequence<Ls...>) {
+    (fwd_col16<ID, int(Ls)>(Z, lds, lane), ...);
 }
 
-// the same for the float64 DCT: B[:, Lc] = C Z[:, Lc] (even/odd butterfly)
-template <int Lc>
-__device__ __forceinline__ void dct_col(const double (&Z)[8][8], double *lds, int lane) {
-    double se[4], de[4];
+// One integer transform's sweep over the zig-zag scan for the lane's block;
+// `out` points at the transform's r_lo..r_hi row of the table.
+// an empty asm that claims to rewrite the block's words: values derived from
+// them cannot be hoisted out of the per-transform loop and kept live across
+// every sweep
+__device__ __forceinline__ void opaque_block(uint32_t (&pix)[8][2]) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        se[m] = Z[m][Lc] + Z[7 - m][Lc];
-        de[m] = Z[m][Lc] - Z[7 - m][Lc];
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc = fma(kDct.c[8 * k + m], (k & 1) ? de[m] : se[m], acc);
-        lds[zz_pos(k, Lc) * 64 + lane] = acc;
-    }
+    for (int x = 0; x < 8; ++x) asm volatile("" : "+v"(pix[x][0]), "+v"(pix[x][1]));
 }
 
-template <size_t... Ls>
-__device__ __forceinline__ void dct_cols(const double (&Z)[8][8], double *lds, int lane, std::index_sequence<Ls...>) {
-    (dct_col<int(Ls)>(Z, lds, lane), ...);
-}
-
-// round-half-to-even(n / L) clipped to [0, 255], exact
-template <int32_t L>
-__device__ __forceinline__ int rne_clip(int n) {
-    const int nc = min(max(n, 0), 255 * L);
-    const uint32_t u = 2u * uint32_t(nc) + uint32_t(L);
-    const uint32_t q = u / uint32_t(2 * L);
-    const bool tie = (u == uint32_t(__umul24(q, uint32_t(2 * L))));
-    return int(q) - int(tie & (q & 1u));
-}
-
-// Integer transform: exact incremental reconstruction over the zig-zag scan.
-struct Pix {
-    uint32_t w[8][2];
-};
-
-// One transform's sweep over the zig-zag scan for the lane's block.  A real
-// (non-inlined) function per transform, so each gets its own register
-// allocation; `out` points at the transform's r_lo..r_hi row of the table.
 template <int ID>
-__device__ __noinline__ void sweep_int(const Pix P, bool active, unsigned long long *out, int r_lo, int r_hi) {
-    const uint32_t (&pix)[8][2] = P.w;
-    int *lds = reinterpret_cast<int *>(g_stage);
-    constexpr int32_t L = Tf<ID>::L();
-    const int lane = threadIdx.x & 63;
-    // forward Y = T A T^T; V_z = Y(k, l) c_k c_l at zig-zag position z -> LDS
-    int Z[8][8];
+__device__ __forceinline__ void sweep_int(const uint32_t (&pix_in)[8][2], bool active, unsigned long long *out,
+                                          int r_lo, int r_hi, int lane) {
+    uint32_t pix[8][2];
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
-        int in[8], out[8];
-#pragma unroll
-        for (int y = 0; y < 8; ++y) in[y] = pix_at(pix, x, y);
-        fwd_full<ID>(in, out);
-#pragma unroll
-        for (int l = 0; l < 8; ++l) Z[x][l] = out[l];
+        pix[x][0] = pix_in[x][0];
+        pix[x][1] = pix_in[x][1];
     }
-    fwd_cols<ID>(Z, lds, lane, std::make_index_sequence<8>{});
+    opaque_block(pix);
+    int16_t *lds = g_stage16;
+    {
+        int Z[8][8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            int in[8], o[8];
+#pragma unroll
+            for (int y = 0; y < 8; ++y) in[y] = pix_at(pix, x, y);
+            fwd_full<ID>(in, o);
+#pragma unroll
+            for (int l = 0; l < 8; ++l) Z[x][l] = o[l];
+        }
+        fwd_cols16<ID>(Z, lds, lane, std::make_index_sequence<8>{});
+    }
     __builtin_amdgcn_wave_barrier();
     int A[8][8];
 #pragma unroll
@@ -263,21 +395,26 @@ __device__ __noinline__ void sweep_int(const Pix P, bool active, unsigned long l
 #pragma unroll
         for (int y = 0; y < 8; ++y) A[x][y] = 0;
     const uint32_t e_pix = pix_energy(pix);
+    const StepEnt *S = kStepDev[ID].s;
+    const IntRoundRegs rc = int_round_regs<ID>();
+    int v = lds[lane];
     for (int j = 0; j < r_hi; ++j) {
-        const int v = lds[j * 64 + lane];
-        const int k = kZZDev.k[j], l = kZZDev.l[j];           // wave-uniform
-        const Mat8 &T = kMatDev[ID];
+        const int vn = lds[((j + 1) & 63) * 64 + lane];     // next step's coefficient
+        const StepEnt &E = S[j];                             // wave-uniform: scalar loads
         int u[8];
 #pragma unroll
-        for (int x = 0; x < 8; ++x) u[x] = v * int(T.m[k][x]);
-        // A += u t_l^T; t_l entries are 0, +-1, +-2 and wave-uniform
-        add_outer(A, u, T.m[l], std::make_index_sequence<8>{});
+        for (int x = 0; x < 8; ++x) u[x] = v * int(E.tk[x]);
+        // operands of known narrow range select the 24-bit multiply(-add)
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+            for (int y = 0; y < 8; ++y) A[x][y] = __mul24(u[x], int(E.w[y])) + A[x][y];
         uint32_t sq = e_pix, cross = 0;
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
             int q[8];
 #pragma unroll
-            for (int y = 0; y < 8; ++y) q[y] = rne_clip<L>(A[x][y]);
+            for (int y = 0; y < 8; ++y) q[y] = rne_clip_int<ID>(A[x][y], rc);
             score_row(q, pix[x][0], pix[x][1], sq, cross);
         }
         unsigned err = sq - 2u * cross;
@@ -285,39 +422,113 @@ __device__ __noinline__ void sweep_int(const Pix P, bool active, unsigned long l
             err = wave_add(active ? err : 0u);
             if (lane == 0 && err) atomicAdd(out + (j + 1 - r_lo), (unsigned long long)err);
         }
+        v = vn;
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-// Exact DCT: float64 incremental reconstruction over the zig-zag scan.
-__device__ __noinline__ void sweep_dct(const Pix P, bool active, unsigned long long *out, int r_lo, int r_hi) {
-    const uint32_t (&pix)[8][2] = P.w;
-    double *lds = g_stage;
-    const int lane = threadIdx.x & 63;
-    {
-        // row pass Z = A C^T with the even/odd butterfly (exact integer sums first)
-        double Z[8][8];
+// ---------------------------------------------------------------- float64 DCT sweep
+//
+// Step j (zig-zag (k, l)) adds B(k,l) C[k][x] C[l][y] to pixel (x, y).  The
+// lane keeps 32 float64 accumulators (four pixel rows) per pass, so the block
+// takes two passes over the scan; the coefficients are staged in LDS 32 at a
+// time (16 KB per wave), each window computed by a column-wise forward that
+// keeps one column of the row pass live.  The forward is repeated per pass and
+// window (its arithmetic, and so every coefficient, is the same each time).
+
+struct DctStep {
+    double ck[8];     // C[k][x]
+    double cl[8];     // C[l][y]
+};
+struct DctStepTab {
+    DctStep s[64];
+};
+constexpr DctStepTab make_dct_steps() {
+    DctStepTab t{};
+    const DctTab c = make_dct();
+    for (int j = 0; j < 64; ++j) {
+        const int k = kZZ[j] >> 3, l = kZZ[j] & 7;
+        for (int x = 0; x < 8; ++x) {
+            t.s[j].ck[x] = c.c[8 * k + x];
+            t.s[j].cl[x] = c.c[8 * l + x];
+        }
+    }
+    return t;
+}
+__device__ constexpr DctStepTab kDctStep = make_dct_steps();
+
+constexpr int kDctWin = 32;                    // coefficients per staged window
+__shared__ double g_stage64[kDctWin * 64];     // [z - window start][lane]
+
+// One column Lc of the forward, restricted to window W: the row pass
+// Z[x] = sum_y A[x][y] C[Lc][y] (even/odd butterfly, exact integer sums first),
+// then B(k, Lc) = sum_x C[k][x] Z[x] for the k whose zig-zag slot is in W.
+template <int W, int Lc>
+__device__ __forceinline__ void dct_fwd_col(const uint32_t (&pix_in)[8][2], double *lds, int lane) {
+    constexpr int lo = W * kDctWin, hi = lo + kDctWin;
+    constexpr bool any = (zz_pos(0, Lc) >= lo && zz_pos(0, Lc) < hi) || (zz_pos(1, Lc) >= lo && zz_pos(1, Lc) < hi) ||
+                         (zz_pos(2, Lc) >= lo && zz_pos(2, Lc) < hi) || (zz_pos(3, Lc) >= lo && zz_pos(3, Lc) < hi) ||
+                         (zz_pos(4, Lc) >= lo && zz_pos(4, Lc) < hi) || (zz_pos(5, Lc) >= lo && zz_pos(5, Lc) < hi) ||
+                         (zz_pos(6, Lc) >= lo && zz_pos(6, Lc) < hi) || (zz_pos(7, Lc) >= lo && zz_pos(7, Lc) < hi);
+    if constexpr (any) {
+        // a fresh opaque copy per column: the butterfly sums shared by columns of
+        // equal parity are recomputed rather than kept live across columns
+        uint32_t pix[8][2];
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
-            int sm[4], dm[4];
+            pix[x][0] = pix_in[x][0];
+            pix[x][1] = pix_in[x][1];
+        }
+        opaque_block(pix);
+        double Z[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            double acc = 0.0;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                sm[m] = pix_at(pix, x, m) + pix_at(pix, x, 7 - m);
-                dm[m] = pix_at(pix, x, m) - pix_at(pix, x, 7 - m);
+                const int sd = (Lc & 1) ? pix_at(pix, x, m) - pix_at(pix, x, 7 - m)
+                                        : pix_at(pix, x, m) + pix_at(pix, x, 7 - m);
+                acc = fma(double(sd), kDct.c[8 * Lc + m], acc);
             }
+            Z[x] = acc;
+        }
+        double se[4], de[4];
 #pragma unroll
-            for (int l = 0; l < 8; ++l) {
+        for (int m = 0; m < 4; ++m) {
+            se[m] = Z[m] + Z[7 - m];
+            de[m] = Z[m] - Z[7 - m];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int z = zz_pos(k, Lc);
+            if (z >= lo && z < hi) {
                 double acc = 0.0;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) acc = fma(double((l & 1) ? dm[m] : sm[m]), kDct.c[8 * l + m], acc);
-                Z[x][l] = acc;
+                for (int m = 0; m < 4; ++m) acc = fma(kDct.c[8 * k + m], (k & 1) ? de[m] : se[m], acc);
+                lds[(z - lo) * 64 + lane] = acc;
             }
         }
-        // column pass B = C Z, written to LDS in zig-zag order
-        dct_cols(Z, lds, lane, std::make_index_sequence<8>{});
     }
-    __builtin_amdgcn_wave_barrier();
-    // two passes over half-blocks of 4 rows keep 32 float64 accumulators live
+}
+
+template <int W, size_t... Ls>
+__device__ __forceinline__ void dct_fwd_window(const uint32_t (&pix)[8][2], double *lds, int lane,
+                                               std::index_sequence<Ls...>) {
+    (dct_fwd_col<W, int(Ls)>(pix, lds, lane), ...);
+}
+
+// Exact DCT: float64 incremental reconstruction over the zig-zag scan.
+__device__ __forceinline__ void sweep_dct(const uint32_t (&pix_in)[8][2], bool active, unsigned long long *out,
+                                          int r_lo, int r_hi, int lane) {
+    uint32_t pix[8][2];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        pix[x][0] = pix_in[x][0];
+        pix[x][1] = pix_in[x][1];
+    }
+    opaque_block(pix);
+    double *lds = g_stage64;
+    const DctStep *S = kDctStep.s;
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
         uint32_t rows[4][2];
@@ -337,75 +548,112 @@ __device__ __noinline__ void sweep_dct(const Pix P, bool active, unsigned long l
         for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int y = 0; y < 8; ++y) A[x][y] = 0.0;
-        for (int j = 0; j < r_hi; ++j) {
-            const double b = lds[j * 64 + lane];
-            const int k = kZZDev.k[j], l = kZZDev.l[j];         // wave-uniform
-            double u[4];
+#pragma unroll 1
+        for (int w = 0; w * kDctWin < r_hi; ++w) {
+            __builtin_amdgcn_wave_barrier();
+            if (w == 0) dct_fwd_window<0>(pix, lds, lane, std::make_index_sequence<8>{});
+            else dct_fwd_window<1>(pix, lds, lane, std::make_index_sequence<8>{});
+            __builtin_amdgcn_wave_barrier();
+            const int j0 = w * kDctWin, j1 = min(r_hi, j0 + kDctWin);
+            for (int j = j0; j < j1; ++j) {
+                const double b = lds[(j - j0) * 64 + lane];
+                const DctStep &E = S[j];                     // wave-uniform: scalar loads
+                double u[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) u[x] = b * kDct.c[8 * k + 4 * h + x];
+                for (int x = 0; x < 4; ++x) u[x] = b * E.ck[4 * h + x];
 #pragma unroll
-            for (int y = 0; y < 8; ++y) {
-                const double cl = kDct.c[8 * l + y];
+                for (int y = 0; y < 8; ++y) {
+                    const double cl = E.cl[y];
 #pragma unroll
-                for (int x = 0; x < 4; ++x) A[x][y] = fma(u[x], cl, A[x][y]);
-            }
-            uint32_t sq = e_half, cross = 0;
+                    for (int x = 0; x < 4; ++x) A[x][y] = fma(u[x], cl, A[x][y]);
+                }
+                uint32_t sq = e_half, cross = 0;
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                int q[8];
+                for (int x = 0; x < 4; ++x) {
+                    int q[8];
 #pragma unroll
-                for (int y = 0; y < 8; ++y)
-                    q[y] = min(max(__double2loint(A[x][y] + 6755399441055744.0), 0), 255);
-                score_row(q, rows[x][0], rows[x][1], sq, cross);
-            }
-            unsigned err = sq - 2u * cross;
-            if (j + 1 >= r_lo) {
-                err = wave_add(active ? err : 0u);
-                if (lane == 0 && err) atomicAdd(out + (j + 1 - r_lo), (unsigned long long)err);
+                    for (int y = 0; y < 8; ++y)
+                        q[y] = min(max(__double2loint(A[x][y] + 6755399441055744.0), 0), 255);
+                    score_row(q, rows[x][0], rows[x][1], sq, cross);
+                }
+                unsigned err = sq - 2u * cross;
+                if (j + 1 >= r_lo) {
+                    err = wave_add(active ? err : 0u);
+                    if (lane == 0 && err) atomicAdd(out + (j + 1 - r_lo), (unsigned long long)err);
+                }
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_batch(const BatchArgs a) {
+// ---------------------------------------------------------------- kernels
+
+struct TileRef {
+    int image;
+    bool active;
+    uint32_t pix[8][2];
+};
+
+// locate the image of a tile (binary search over the tiles' start indices) and
+// load the lane's 8x8 block
+__device__ __forceinline__ void load_tile(const BatchArgs &a, int tile, int lane, TileRef &t) {
+    int lo = 0, hi = a.n_images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.img[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
+    }
+    t.image = lo;
+    const BatchImg &I = a.img[lo];
+    const int b = (tile - I.tile_start) * 64 + lane;
+    t.active = b < I.nblocks;
+    const int bb = t.active ? b : 0;
+    const int by = bb / I.nbx, bx = bb - by * I.nbx;
+    const uint8_t *src = a.base + I.offset + int64_t(8 * by) * I.pitch + 8 * bx;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const u32x2 v = *(const u32x2 *)(src + int64_t(x) * I.pitch);
+        t.pix[x][0] = v.x;
+        t.pix[x][1] = v.y;
+    }
+}
+
+// integer transforms: items are (tile, group) with group g taking the integer
+// transforms g, g + split, ... of the list
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_int(const BatchArgs a) {
     const int lane = threadIdx.x;
     const int items = a.total_tiles * a.split;
+    const int nr = a.r_hi - a.r_lo + 1;
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
         const int tile = it / a.split, grp = it - tile * a.split;
-        int i = 0;                                              // image of this tile (uniform)
-        int lo = 0, hi = a.n_images - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.img[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
-        }
-        i = lo;
-        const BatchImg &I = a.img[i];
-        const int b = (tile - I.tile_start) * 64 + lane;
-        const bool active = b < I.nblocks;
-        const int bb = active ? b : 0;
-        const int by = bb / I.nbx, bx = bb - by * I.nbx;
-        const uint8_t *src = a.base + I.offset + int64_t(8 * by) * I.pitch + 8 * bx;
-        Pix P;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const u32x2 v = *(const u32x2 *)(src + int64_t(x) * I.pitch);
-            P.w[x][0] = v.x;
-            P.w[x][1] = v.y;
-        }
-        const int nr = a.r_hi - a.r_lo + 1;
-        for (int ti = grp; ti < a.n_transforms; ti += a.split) {
-            unsigned long long *out = a.sse + (int64_t(i) * a.n_transforms + ti) * nr;
+        TileRef T;
+        load_tile(a, tile, lane, T);
+        for (int ii = grp; ii < a.n_int; ii += a.split) {
+            const int ti = a.int_pos[ii];
+            unsigned long long *out = a.sse + (int64_t(T.image) * a.n_transforms + ti) * nr;
             switch (a.tids[ti]) {
-                case ADCT_DCT: sweep_dct(P, active, out, a.r_lo, a.r_hi); break;
-                case ADCT_T1: sweep_int<ADCT_T1>(P, active, out, a.r_lo, a.r_hi); break;
-                case ADCT_T2: sweep_int<ADCT_T2>(P, active, out, a.r_lo, a.r_hi); break;
-                case ADCT_LO: sweep_int<ADCT_LO>(P, active, out, a.r_lo, a.r_hi); break;
-                case ADCT_T6: sweep_int<ADCT_T6>(P, active, out, a.r_lo, a.r_hi); break;
-                case ADCT_RDCT: sweep_int<ADCT_RDCT>(P, active, out, a.r_lo, a.r_hi); break;
-                default: sweep_int<ADCT_T4>(P, active, out, a.r_lo, a.r_hi); break;
+                case ADCT_T1: sweep_int<ADCT_T1>(T.pix, T.active, out, a.r_lo, a.r_hi, lane); break;
+                case ADCT_T2: sweep_int<ADCT_T2>(T.pix, T.active, out, a.r_lo, a.r_hi, lane); break;
+                case ADCT_LO: sweep_int<ADCT_LO>(T.pix, T.active, out, a.r_lo, a.r_hi, lane); break;
+                case ADCT_T6: sweep_int<ADCT_T6>(T.pix, T.active, out, a.r_lo, a.r_hi, lane); break;
+                case ADCT_RDCT: sweep_int<ADCT_RDCT>(T.pix, T.active, out, a.r_lo, a.r_hi, lane); break;
+                default: sweep_int<ADCT_T4>(T.pix, T.active, out, a.r_lo, a.r_hi, lane); break;
             }
         }
+    }
+}
+
+// the exact DCT: items are (tile, DCT entry of the list)
+__global__ __launch_bounds__(64) void k_batch_dct(const BatchArgs a) {
+    const int lane = threadIdx.x;
+    const int items = a.total_tiles * a.n_dct;
+    const int nr = a.r_hi - a.r_lo + 1;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int tile = it / a.n_dct, d = it - tile * a.n_dct;
+        TileRef T;
+        load_tile(a, tile, lane, T);
+        unsigned long long *out = a.sse + (int64_t(T.image) * a.n_transforms + a.dct_pos[d]) * nr;
+        sweep_dct(T.pix, T.active, out, a.r_lo, a.r_hi, lane);
     }
 }
 
@@ -425,16 +673,31 @@ int device_cus() {
     return cus;
 }
 
+// zero fill, then the DCT kernel (if the list has the DCT), then the integer
+// kernel (if it has integer transforms).  wgs_per_cu sets the integer kernel's
+// resident single-wave workgroups per compute unit; the DCT kernel fills every
+// slot its 32 KB of LDS allows.
 adct_status enqueue(const BatchArgs &a, int wgs_per_cu, hipStream_t s) {
     const int64_t n = int64_t(a.n_images) * a.n_transforms * (a.r_hi - a.r_lo + 1);
     hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a.sse, n);
     ADCT_HIP(hipGetLastError());
     const int cus = device_cus();
     if (cus <= 0) return fail(ADCT_EDEVICE, "cannot query the device");
-    const int64_t items = int64_t(a.total_tiles) * a.split;
-    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(items, int64_t(wgs_per_cu) * cus)));
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64), 0, s, a);
-    ADCT_HIP(hipGetLastError());
+    if (a.n_dct > 0) {
+        int per_cu = 0;
+        ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_dct, 64, 0));
+        if (per_cu < 1) per_cu = 1;
+        const int64_t items = int64_t(a.total_tiles) * a.n_dct;
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(items, int64_t(per_cu) * cus)));
+        hipLaunchKernelGGL(k_batch_dct, dim3(grid), dim3(64), 0, s, a);
+        ADCT_HIP(hipGetLastError());
+    }
+    if (a.n_int > 0) {
+        const int64_t items = int64_t(a.total_tiles) * a.split;
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(items, int64_t(wgs_per_cu) * cus)));
+        hipLaunchKernelGGL(k_batch_int, dim3(grid), dim3(64), 0, s, a);
+        ADCT_HIP(hipGetLastError());
+    }
     return ADCT_OK;
 }
 
@@ -476,6 +739,8 @@ adct_status build_args(const uint8_t *base, const adct_plane *images, int n_imag
         const int id = transforms[t];
         if (id < ADCT_DCT || id > ADCT_T4) return fail(ADCT_EINVAL, "unknown or custom transform in a batch");
         a->tids[t] = id;
+        if (id == ADCT_DCT) a->dct_pos[a->n_dct++] = t;
+        else a->int_pos[a->n_int++] = t;
     }
     int tiles = 0;
     for (int i = 0; i < n_images; ++i) {
@@ -508,7 +773,7 @@ adct_status adct_evaluate_batch(const uint8_t *base, const adct_plane *images, i
     if (st) return st;
     if (wgs_per_cu < 1 || wgs_per_cu > 16) return fail(ADCT_ERANGE, "wgs_per_cu must be in [1, 16]");
     if (split < 1 || split > n_transforms) return fail(ADCT_ERANGE, "split must be in [1, n_transforms]");
-    a.split = split;
+    a.split = std::min(split, std::max(a.n_int, 1));
     return enqueue(a, wgs_per_cu, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -535,9 +800,10 @@ adct_status adct_batch_plan_create(const uint8_t *base, const adct_plane *images
         }
         double best = 1e30;
         int best_w = 4, best_s = 1;
-        for (int split = 1; split <= p->args.n_transforms; ++split) {
-            if (p->args.n_transforms % split) continue;
-            for (int w : {2, 3, 4, 5, 6, 8}) {
+        const int n_split = std::max(p->args.n_int, 1);
+        for (int split = 1; split <= n_split; ++split) {
+            if (n_split % split) continue;
+            for (int w : {4, 6, 8, 12, 16}) {
                 BatchArgs a = p->args;
                 a.split = split;
                 st = enqueue(a, w, s);                         // warm
