@@ -299,12 +299,30 @@ def evaluate(img: np.ndarray, t: np.ndarray, r: int, step: int = 0) -> dict:
             "mse_real": float(np.mean(d * d))}
 
 
+def forward_dct(blocks: np.ndarray) -> np.ndarray:
+    """B = C A C^T with the orthonormal DCT (Sec. 2) in float64, except the four
+    coefficients (k, l) in {0, 4}^2, which are rational and computed exactly.
+
+    a_0 = 1/sqrt(8) and a_4 cos((2n+1) 4 pi / 16) = +-1/sqrt(8), so every basis
+    entry of those four is +-1/8 and B(k, l) = (sum of +-pixels) / 8 exactly.
+    The quantiser's half-step cases land on them (B(0,0)/16 is a half for one
+    8-bit block in 128); float64 would decide such a tie by its own rounding
+    of 1/sqrt(8)^2."""
+    b = forward_real(blocks, dct_matrix())
+    a = np.asarray(blocks, dtype=np.int64)
+    sign = {0: np.ones(N, dtype=np.int64), 4: np.array([1, -1, -1, 1, 1, -1, -1, 1], dtype=np.int64)}
+    for k in (0, 4):
+        for l in (0, 4):
+            b[:, k, l] = np.einsum("x,bxy,y->b", sign[k], a, sign[l]) / 8.0
+    return b
+
+
 def evaluate_dct(img: np.ndarray, r: int, step: int = 0) -> dict:
     """The same pipeline with the exact (orthonormal) DCT in float64."""
     h, w = img.shape
     c = dct_matrix()
     blocks = to_blocks(img)
-    b = forward_real(blocks, c)
+    b = forward_dct(blocks)
     b_zz = take_zigzag(b, r)
     if step > 0:
         b_zz_kept = _round_half_away(b_zz / step) * step

@@ -455,26 +455,25 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
     int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     if (gw >= total) return;                               // whole wave leaves
     // two pixel buffers used in turn: the next tile loads into one while the
-    // current tile is transformed from the other
+    // current tile is transformed from the other.  The next loads are issued
+    // on every pass (a wave's last pass re-reads its current tile), so no
+    // branch joins paths with different loads in flight and the waits for the
+    // current tile leave the next tile's loads outstanding.
     uint32_t pa[8][2], pb[8][2];
     Tile ta = tile_of(a, gw, lane), tb = ta;
     if constexpr (MODE != kDecode) load_tile(a, ta, pa);
     while (true) {
         int nxt = gw + stride;
         bool more = nxt < total;                           // wave-uniform
-        if (more) {
-            tb = tile_of(a, nxt, lane);
-            if constexpr (MODE != kDecode) load_tile(a, tb, pb);
-        }
+        tb = tile_of(a, more ? nxt : gw, lane);
+        if constexpr (MODE != kDecode) load_tile(a, tb, pb);
         process_tile<ID, BAND, QUANT, MODE>(a, ta, pa);
         if (!more) break;
         gw = nxt;
         nxt = gw + stride;
         more = nxt < total;
-        if (more) {
-            ta = tile_of(a, nxt, lane);
-            if constexpr (MODE != kDecode) load_tile(a, ta, pa);
-        }
+        ta = tile_of(a, more ? nxt : gw, lane);
+        if constexpr (MODE != kDecode) load_tile(a, ta, pa);
         process_tile<ID, BAND, QUANT, MODE>(a, tb, pb);
         if (!more) break;
         gw = nxt;

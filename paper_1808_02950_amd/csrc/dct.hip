@@ -29,6 +29,7 @@ namespace adct {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 // Bank-conflict-free LDS layouts of K (64 x 64 floats each):
 //  forward reads  (c = 16 ct + n, p with p % 16 = 4 g + s % 4, p / 16 = s / 4)
@@ -49,6 +50,9 @@ struct DTile {
     uint32_t in_off, out_off;   // byte offset of the block's top-left pixel
 };
 
+// Tile gw of the launch: frame and plane are wave-uniform; the wave's first
+// block comes from one scalar division, and lane n's block is at most one
+// block-row further when the plane is at least 16 blocks wide.
 __device__ __forceinline__ DTile dtile_of(const DctArgs &a, int gw, int n) {
     DTile t;
     t.f = gw / a.waves_per_frame;
@@ -57,18 +61,150 @@ __device__ __forceinline__ DTile dtile_of(const DctArgs &a, int gw, int n) {
     while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
     t.p = p;
     const PlaneArg &P = a.pl[p];
-    t.b = (w - P.wave_start) * 16 + n;
+    const int b0 = (w - P.wave_start) * 16;
+    const int by0 = b0 / P.nbx;
+    const int bx0 = b0 - by0 * P.nbx;
+    t.b = b0 + n;
     t.active = t.b < P.nblocks;
-    const int bb = t.active ? t.b : 0;
-    const int by = bb / P.nbx;
-    const int bx = bb - by * P.nbx;
+    int by, bx;
+    if (P.nbx >= 16) {
+        bx = bx0 + n;
+        by = by0;
+        if (bx >= P.nbx) {
+            bx -= P.nbx;
+            ++by;
+        }
+    } else {
+        by = t.b / P.nbx;
+        bx = t.b - by * P.nbx;
+    }
+    if (!t.active) by = bx = 0;
     t.in_off = __umul24(uint32_t(8 * by), uint32_t(P.pitch_in)) + uint32_t(8 * bx);
     t.out_off = __umul24(uint32_t(8 * by), uint32_t(P.pitch_out)) + uint32_t(8 * bx);
     return t;
 }
 
+// the lane's 16 pixels: rows 2t + g/2, columns 4(g%2) .. + 3 (inactive lanes
+// read block (0, 0) of the plane, in bounds; the values are never used)
+// (a wave-uniform plane base plus a 32-bit lane offset, so the loads take the
+// scalar-base addressing form)
+__device__ __forceinline__ void load_dtile(const DctArgs &a, const DTile &T, int g, uint32_t (&px)[4]) {
+    const PlaneArg &P = a.pl[T.p];
+    const uint8_t *base = a.in + int64_t(T.f) * a.fs_in + P.in_off;
+    const uint32_t off = T.in_off + __umul24(uint32_t(g >> 1), uint32_t(P.pitch_in)) + 4u * uint32_t(g & 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        px[t] = __builtin_nontemporal_load((const uint32_t *)(base + (off + 2u * uint32_t(t) * uint32_t(P.pitch_in))));
+}
+
+// one 16-block tile: forward, zonal retention (+ quantiser), inverse, round,
+// clip, store, squared error
+template <int MODE, bool ONE>
+__device__ __forceinline__ void process_dtile(const DctArgs &a, const DTile &T, const uint32_t (&px)[4],
+                                              const float *kf, const float *ki, const float (&kfr)[16],
+                                              const float (&kir)[16], int n, int g, int lane) {
+    const PlaneArg &P = a.pl[T.p];
+    const int64_t gblk = int64_t(T.f) * a.blocks_per_frame + P.block_off + T.b;
+    const bool store_coef = (a.coef_f != nullptr) | (a.coef_q != nullptr);   // wave-uniform
+    const int nct = ONE ? 1 : (a.r + 15) >> 4;             // coefficient tiles
+    f32x4 acc[4] = {};                                      // inverse accumulators, pixel tiles
+    for (int ct = 0; ct < nct; ++ct) {
+        f32x4 coef = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE != kDecode) {
+            // forward: coef[c = 16ct + 4g + i] for block n, as four
+            // independent accumulation chains (one per pixel row pair)
+            f32x4 part[4] = {};
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int p = 16 * (s >> 2) + 4 * g + (s & 3);
+                const float av = ONE ? kfr[s] : kf[fwd_addr(16 * ct + n, p)];
+                const float bv = float((px[s >> 2] >> (8 * (s & 3))) & 0xffu);
+                part[s >> 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, part[s >> 2], 0, 0, 0);
+            }
+            coef = (part[0] + part[1]) + (part[2] + part[3]);
+        } else {
+            // decode: coefficients come from memory
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = 16 * ct + 4 * g + i;
+                if (T.active && c < a.r) {
+                    coef[i] = a.step ? float(a.coef_q[gblk * a.r + c]) * float(a.step)
+                                     : a.coef_f[gblk * a.r + c];
+                }
+            }
+        }
+        // zonal retention (+ quantiser) and coefficient output
+        float qv[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = 16 * ct + 4 * g + i;
+            if (c >= a.r) coef[i] = 0.f;
+            if constexpr (MODE != kDecode)
+                if (a.step) qv[i] = copysignf(floorf(fabsf(coef[i]) * a.inv_step + 0.5f), coef[i]);
+        }
+        if constexpr (MODE != kDecode) {
+            if (store_coef) {
+                const int64_t cb = gblk * a.r + 16 * ct + 4 * g;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (T.active && 16 * ct + 4 * g + i < a.r) {
+                        if (a.coef_q) a.coef_q[cb + i] = int16_t(qv[i]);
+                        if (a.coef_f) a.coef_f[cb + i] = coef[i];
+                    }
+                }
+            }
+            if (a.step) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) coef[i] = qv[i] * float(a.step);
+            }
+        }
+        if constexpr (MODE == kEncode) continue;
+        // inverse: acc[t] (pixels 16t + 4g + i) += sum_c K[c][p] coef_c
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float av = ONE ? kir[4 * t + s] : ki[inv_addr(16 * t + n, 16 * ct + 4 * g + s)];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, coef[s], acc[t], 0, 0, 0);
+            }
+    }
+    if constexpr (MODE == kEncode) return;
+
+    // ---- round, clip, store 4 pixels per pixel tile, squared error.  Clamping
+    // to [0, 255] first and adding 1.5 * 2^23 leaves round-half-to-even of the
+    // value in the low byte of the float's bits.
+    uint32_t sq = 0, cross = 0;
+    uint8_t *dbase = a.out ? a.out + int64_t(T.f) * a.fs_out + P.out_off : nullptr;   // wave-uniform
+    const uint32_t doff = T.out_off + __umul24(uint32_t(g >> 1), uint32_t(P.pitch_out)) + 4u * uint32_t(g & 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = __float_as_uint(__builtin_amdgcn_fmed3f(acc[t][i], 0.f, 255.f) + 12582912.0f);
+        const uint32_t lo = __builtin_amdgcn_perm(v[1], v[0], 0x0c0c0400u);   // bytes v0.b0, v1.b0
+        const uint32_t hi = __builtin_amdgcn_perm(v[3], v[2], 0x04000c0cu);   // bytes v2.b0, v3.b0 at 2, 3
+        const uint32_t word = lo | hi;
+        if (T.active && dbase)
+            __builtin_nontemporal_store(word, (uint32_t *)(dbase + (doff + 2u * uint32_t(t) * uint32_t(P.pitch_out))));
+        if constexpr (MODE == kEvaluate) {
+            sq = __builtin_amdgcn_udot4(word, word, sq, false);
+            sq = __builtin_amdgcn_udot4(px[t], px[t], sq, false);
+            cross = __builtin_amdgcn_udot4(word, px[t], cross, false);
+        }
+    }
+    if constexpr (MODE == kEvaluate) {
+        unsigned e = T.active ? sq - 2u * cross : 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+        if (lane == 0 && e) atomicAdd(a.sse + int64_t(T.f) * a.n_planes + T.p, (unsigned long long)e);
+    }
+}
+
 // ONE: r <= 16, a single coefficient tile: every operand of K a lane needs
-// (16 forward, 16 inverse) is read from LDS once into registers.
+// (16 forward, 16 inverse) is read from LDS once into registers.  Persistent:
+// each wave walks tiles gw, gw + stride, ... and loads the next tile's pixels
+// into one buffer while it transforms the current tile from the other.
 template <int MODE, bool ONE>
 __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
     __shared__ float kf[64 * 64];
@@ -85,7 +221,7 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int total = a.n_frames * a.waves_per_frame;
-    const int nct = ONE ? 1 : (a.r + 15) >> 4;             // coefficient tiles
+    const int stride = int(gridDim.x) * 4;
     float kfr[16], kir[16];
     if constexpr (ONE) {
 #pragma unroll
@@ -94,107 +230,278 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int s = 0; s < 4; ++s) kir[4 * t + s] = ki[inv_addr(16 * t + n, 4 * g + s)];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) kfr[s] = kir[s] = 0.f;
     }
-    for (int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-         gw < total; gw += int(gridDim.x) * 4) {
-        const DTile T = dtile_of(a, gw, n);
-        const PlaneArg &P = a.pl[T.p];
-        const int64_t gblk = int64_t(T.f) * a.blocks_per_frame + P.block_off + T.b;
+    int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (gw >= total) return;                                // whole wave leaves
+    uint32_t pa[4] = {0u, 0u, 0u, 0u}, pb[4] = {0u, 0u, 0u, 0u};
+    DTile ta = dtile_of(a, gw, n), tb = ta;
+    if constexpr (MODE != kDecode) load_dtile(a, ta, g, pa);
+    // the next loads are issued on every pass (a wave's last pass re-reads its
+    // current tile): no branch joins paths with different loads in flight, so
+    // the waits for the current tile leave the next tile's loads outstanding
+    while (true) {
+        int nxt = gw + stride;
+        bool more = nxt < total;                            // wave-uniform
+        tb = dtile_of(a, more ? nxt : gw, n);
+        if constexpr (MODE != kDecode) load_dtile(a, tb, g, pb);
+        process_dtile<MODE, ONE>(a, ta, pa, kf, ki, kfr, kir, n, g, lane);
+        if (!more) break;
+        gw = nxt;
+        nxt = gw + stride;
+        more = nxt < total;
+        ta = dtile_of(a, more ? nxt : gw, n);
+        if constexpr (MODE != kDecode) load_dtile(a, ta, g, pa);
+        process_dtile<MODE, ONE>(a, tb, pb, kf, ki, kfr, kir, n, g, lane);
+        if (!more) break;
+        gw = nxt;
+    }
+}
 
-        // ---- the lane's 16 pixels: rows 2t + g/2, columns 4(g%2) .. + 3
-        uint32_t px[4] = {0u, 0u, 0u, 0u};
-        if constexpr (MODE != kDecode) {
-            const uint8_t *src = a.in + int64_t(T.f) * a.fs_in + P.in_off + T.in_off +
-                                 (g >> 1) * P.pitch_in + 4 * (g & 1);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                px[t] = __builtin_nontemporal_load((const uint32_t *)(src + 2 * t * P.pitch_in));
-        }
+// ---------------------------------------------------------------- split-bfloat16 form
+//
+// For r <= 16 with a quantiser step that is a power of two of at least 8, the
+// same products run on the bfloat16 matrix cores without losing float32
+// accuracy:
+//  * every float32 entry of K is the exact sum of three bfloat16 terms (each
+//    rounding keeps eight more bits), so K x = K1 x + K2 x + K3 x;
+//  * pixels (integers below 256) are exact in bfloat16;
+//  * a quantised coefficient q * step with |q| <= 255 and step = 2^e is exact
+//    in bfloat16.
+// Every product is therefore exact and accumulates in float32, as in the
+// float32 form.  Decoding reads q from memory, where |q| may exceed 255: there
+// q * step is split into two exact bfloat16 terms, the second zero for every q
+// the encoder writes, so decode repeats the evaluation's sums exactly.  Lane
+// l = 16 g + n works on block n:
+//  forward  v_mfma_f32_16x16x32_bf16, two halves h: K slot 8 g + j is pixel
+//           (row 2 g + h, column j); the lane feeds its own two block rows;
+//           result rows 4 g + i = coefficients 4 g + i of block n;
+//  inverse  v_mfma_f32_16x16x16_bf16 per pixel tile t: K slot 4 g + i is
+//           coefficient 4 g + i, exactly the lane's forward result; result row
+//           4 g + i of tile t is pixel (row 2 g + t / 2, column 4 (t % 2) + i),
+//           so the lane ends with the same two block rows it loaded.
 
-        f32x4 acc[4] = {};                                  // inverse accumulators, pixel tiles
-        for (int ct = 0; ct < nct; ++ct) {
-            f32x4 coef = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (MODE != kDecode) {
-                // forward: coef[c = 16ct + 4g + i] for block n, as four
-                // independent accumulation chains (one per pixel row pair)
-                f32x4 part[4] = {};
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x4 mma32(const uint4 a, const uint4 b, const f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                   c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma16(const uint2 a, const uint2 b, const f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(i16x4, a), __builtin_bit_cast(i16x4, b),
+                                                     c, 0, 0, 0);
+}
+
+// two float32 -> two bfloat16 (round to nearest even)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// k = t[0] + t[1] + t[2] exactly, each term bfloat16 (as raw bits)
+__device__ __forceinline__ void split3(float k, uint32_t (&t)[3]) {
+    float r = k;
 #pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const int p = 16 * (s >> 2) + 4 * g + (s & 3);
-                    const float av = ONE ? kfr[s] : kf[fwd_addr(16 * ct + n, p)];
-                    const float bv = float((px[s >> 2] >> (8 * (s & 3))) & 0xffu);
-                    part[s >> 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, part[s >> 2], 0, 0, 0);
-                }
-                coef = (part[0] + part[1]) + (part[2] + part[3]);
-            } else {
-                // decode: coefficients come from memory
+    for (int s = 0; s < 3; ++s) {
+        const __bf16 h = (__bf16)r;
+        t[s] = __builtin_bit_cast(uint16_t, h);
+        r -= float(h);
+    }
+}
+
+// the 8 pixels of one block row (two words) as bfloat16 operand slots 0..7
+__device__ __forceinline__ uint4 row_bf16(uint32_t w0, uint32_t w1) {
+    uint4 r;
+    r.x = pack_bf16(float(w0 & 0xffu), float((w0 >> 8) & 0xffu));
+    r.y = pack_bf16(float((w0 >> 16) & 0xffu), float(w0 >> 24));
+    r.z = pack_bf16(float(w1 & 0xffu), float((w1 >> 8) & 0xffu));
+    r.w = pack_bf16(float((w1 >> 16) & 0xffu), float(w1 >> 24));
+    return r;
+}
+
+struct KOps {
+    uint4 f[3][2];    // forward A operand [split][half]
+    uint2 i[3][4];    // inverse A operand [split][pixel tile]
+};
+
+// the lane's operands of K, computed from C as the float32 products used by
+// the float32 form
+__device__ __forceinline__ void make_kops(const DctArgs &a, int lane, KOps &K) {
+    const int row = lane & 15, g = lane >> 4;
+    {
+        const int kc = kZZ[row] >> 3, lc = kZZ[row] & 7;   // forward row = coefficient
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int c = 16 * ct + 4 * g + i;
-                    if (T.active && c < a.r) {
-                        coef[i] = a.step ? float(a.coef_q[gblk * a.r + c]) * float(a.step)
-                                         : a.coef_f[gblk * a.r + c];
-                    }
-                }
+        for (int h = 0; h < 2; ++h) {
+            uint32_t e[3][8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint32_t t[3];
+                split3(a.C[8 * kc + 2 * g + h] * a.C[8 * lc + j], t);
+#pragma unroll
+                for (int s = 0; s < 3; ++s) e[s][j] = t[s];
             }
-            // zonal retention (+ quantiser) and coefficient output
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                K.f[s][h] = uint4{e[s][0] | (e[s][1] << 16), e[s][2] | (e[s][3] << 16), e[s][4] | (e[s][5] << 16),
+                                  e[s][6] | (e[s][7] << 16)};
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {                           // inverse row = pixel of tile t
+        const int x = 2 * (row >> 2) + (t >> 1), y = 4 * (t & 1) + (row & 3);
+        uint32_t e[3][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int z = 4 * g + i, kc = kZZ[z] >> 3, lc = kZZ[z] & 7;
+            uint32_t tt[3];
+            split3(a.C[8 * kc + x] * a.C[8 * lc + y], tt);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) e[s][i] = tt[s];
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) K.i[s][t] = uint2{e[s][0] | (e[s][1] << 16), e[s][2] | (e[s][3] << 16)};
+    }
+}
+
+// the lane's two block rows 2g, 2g+1 (8 bytes each)
+__device__ __forceinline__ void load_rows(const DctArgs &a, const DTile &T, int g, u32x2 (&px)[2]) {
+    const PlaneArg &P = a.pl[T.p];
+    const uint8_t *base = a.in + int64_t(T.f) * a.fs_in + P.in_off;
+    const uint32_t off = T.in_off + __umul24(uint32_t(2 * g), uint32_t(P.pitch_in));
+    px[0] = __builtin_nontemporal_load((const u32x2 *)(base + off));
+    px[1] = __builtin_nontemporal_load((const u32x2 *)(base + (off + uint32_t(P.pitch_in))));
+}
+
+template <int MODE>
+__device__ __forceinline__ void process_rows(const DctArgs &a, const DTile &T, const u32x2 (&px)[2],
+                                             const KOps &K, int g, int lane) {
+    const PlaneArg &P = a.pl[T.p];
+    const int64_t cb = (int64_t(T.f) * a.blocks_per_frame + P.block_off + T.b) * a.r + 4 * g;
+    const float step = float(a.step);
+    float bv[4];                                            // dequantised coefficients 4g..4g+3
+    if constexpr (MODE != kDecode) {
+        // forward, smallest split first
+        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = c0;
+        const uint4 p0 = row_bf16(px[0].x, px[0].y), p1 = row_bf16(px[1].x, px[1].y);
+#pragma unroll
+        for (int s = 2; s >= 0; --s) {
+            c0 = mma32(K.f[s][0], p0, c0);
+            c1 = mma32(K.f[s][1], p1, c1);
+        }
+        f32x4 coef = c0 + c1;
+        // zonal retention, quantiser, coefficient output
+        float qv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (4 * g + i >= a.r) coef[i] = 0.f;
+            qv[i] = copysignf(floorf(fabsf(coef[i]) * a.inv_step + 0.5f), coef[i]);
+            bv[i] = qv[i] * step;
+        }
+        if ((a.coef_f != nullptr) | (a.coef_q != nullptr)) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int c = 16 * ct + 4 * g + i;
-                float v = coef[i];
-                if (c >= a.r) v = 0.f;
-                if constexpr (MODE != kDecode) {
-                    if (T.active && c < a.r) {
-                        if (a.coef_f) a.coef_f[gblk * a.r + c] = v;
-                        if (a.step) {
-                            const float q = copysignf(floorf(fabsf(v) * a.inv_step + 0.5f), v);
-                            if (a.coef_q) a.coef_q[gblk * a.r + c] = int16_t(q);
-                            v = q * float(a.step);
-                        }
-                    } else if (a.step) {
-                        v = 0.f;
-                    }
+                if (T.active && 4 * g + i < a.r) {
+                    if (a.coef_q) a.coef_q[cb + i] = int16_t(qv[i]);
+                    if (a.coef_f) a.coef_f[cb + i] = coef[i];
                 }
-                coef[i] = v;
             }
-            if constexpr (MODE == kEncode) continue;
-            // inverse: acc[t] (pixels 16t + 4g + i) += sum_c K[c][p] coef_c
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float av = ONE ? kir[4 * t + s] : ki[inv_addr(16 * t + n, 16 * ct + 4 * g + s)];
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, coef[s], acc[t], 0, 0, 0);
-                }
         }
-        if constexpr (MODE == kEncode) continue;
-
-        // ---- round, clip, store 4 pixels per pixel tile, squared error
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            bv[i] = (T.active && 4 * g + i < a.r) ? float(a.coef_q[cb + i]) * step : 0.f;
+    }
+    if constexpr (MODE == kEncode) return;
+    const uint2 bhi = {pack_bf16(bv[0], bv[1]), pack_bf16(bv[2], bv[3])};
+    uint2 blo = {0u, 0u};
+    if constexpr (MODE == kDecode) {
+        float r[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t h = (i & 1) ? (i < 2 ? bhi.x : bhi.y) >> 16 : (i < 2 ? bhi.x : bhi.y) & 0xffffu;
+            r[i] = bv[i] - __uint_as_float(h << 16);
+        }
+        blo = uint2{pack_bf16(r[0], r[1]), pack_bf16(r[2], r[3])};
+    }
+    // inverse, smallest split first
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 2; s >= 0; --s) {
+            acc[t] = mma16(K.i[s][t], bhi, acc[t]);
+            if constexpr (MODE == kDecode) acc[t] = mma16(K.i[s][t], blo, acc[t]);
+        }
+    }
+    // round (clamp, then 1.5 * 2^23 leaves the rounded value in the low byte),
+    // store the two rows, squared error
+    uint32_t w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = __float_as_uint(__builtin_amdgcn_fmed3f(acc[t][i], 0.f, 255.f) + 12582912.0f);
+        w[t] = __builtin_amdgcn_perm(v[1], v[0], 0x0c0c0400u) | __builtin_amdgcn_perm(v[3], v[2], 0x04000c0cu);
+    }
+    uint8_t *dbase = a.out ? a.out + int64_t(T.f) * a.fs_out + P.out_off : nullptr;   // wave-uniform
+    if (T.active && dbase) {
+        const uint32_t doff = T.out_off + __umul24(uint32_t(2 * g), uint32_t(P.pitch_out));
+        __builtin_nontemporal_store(u32x2{w[0], w[1]}, (u32x2 *)(dbase + doff));
+        __builtin_nontemporal_store(u32x2{w[2], w[3]}, (u32x2 *)(dbase + (doff + uint32_t(P.pitch_out))));
+    }
+    if constexpr (MODE == kEvaluate) {
         uint32_t sq = 0, cross = 0;
-        uint8_t *dst = a.out ? a.out + int64_t(T.f) * a.fs_out + P.out_off + T.out_off +
-                                   (g >> 1) * P.pitch_out + 4 * (g & 1)
-                             : nullptr;
+        const uint32_t o[4] = {px[0].x, px[0].y, px[1].x, px[1].y};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            uint32_t word = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float r = __builtin_amdgcn_fmed3f(rintf(acc[t][i]), 0.f, 255.f);
-                word |= uint32_t(r) << (8 * i);
-            }
-            if (T.active && dst) __builtin_nontemporal_store(word, (uint32_t *)(dst + 2 * t * P.pitch_out));
-            if constexpr (MODE == kEvaluate) {
-                sq = __builtin_amdgcn_udot4(word, word, sq, false);
-                sq = __builtin_amdgcn_udot4(px[t], px[t], sq, false);
-                cross = __builtin_amdgcn_udot4(word, px[t], cross, false);
-            }
+            sq = __builtin_amdgcn_udot4(w[t], w[t], sq, false);
+            sq = __builtin_amdgcn_udot4(o[t], o[t], sq, false);
+            cross = __builtin_amdgcn_udot4(w[t], o[t], cross, false);
         }
-        if constexpr (MODE == kEvaluate) {
-            unsigned e = T.active ? sq - 2u * cross : 0u;
+        unsigned e = T.active ? sq - 2u * cross : 0u;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-            if (lane == 0 && e) atomicAdd(a.sse + int64_t(T.f) * a.n_planes + T.p, (unsigned long long)e);
-        }
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+        if (lane == 0 && e) atomicAdd(a.sse + int64_t(T.f) * a.n_planes + T.p, (unsigned long long)e);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_dct_bf16(const DctArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int total = a.n_frames * a.waves_per_frame;
+    const int stride = int(gridDim.x) * 4;
+    int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (gw >= total) return;                                // whole wave leaves
+    KOps K;
+    make_kops(a, lane, K);
+    u32x2 pa[2] = {}, pb[2] = {};
+    DTile ta = dtile_of(a, gw, n), tb = ta;
+    if constexpr (MODE != kDecode) load_rows(a, ta, g, pa);
+    // the next loads are issued on every pass (a wave's last pass re-reads its
+    // current tile), as in the float32 form
+    while (true) {
+        int nxt = gw + stride;
+        bool more = nxt < total;                            // wave-uniform
+        tb = dtile_of(a, more ? nxt : gw, n);
+        if constexpr (MODE != kDecode) load_rows(a, tb, g, pb);
+        process_rows<MODE>(a, ta, pa, K, g, lane);
+        if (!more) break;
+        gw = nxt;
+        nxt = gw + stride;
+        more = nxt < total;
+        ta = dtile_of(a, more ? nxt : gw, n);
+        if constexpr (MODE != kDecode) load_rows(a, ta, g, pa);
+        process_rows<MODE>(a, tb, pb, K, g, lane);
+        if (!more) break;
+        gw = nxt;
     }
 }
 
@@ -217,8 +524,35 @@ adct_status launch_dct_kernel(const DctArgs &a, int total_waves, hipStream_t s) 
     return ADCT_OK;
 }
 
+// the split-bfloat16 form: r <= 16 and a power-of-two step of at least 8, so
+// that every quantised level the encoder writes has |q| <= 255 (decoding a
+// quantised stream also needs the levels, which it reads as int16)
+bool bf16_form(const DctArgs &a) {
+    return a.r <= 16 && a.step >= 8 && (a.step & (a.step - 1)) == 0;
+}
+
+template <int M>
+adct_status launch_dct_bf16(const DctArgs &a, int total_waves, hipStream_t s) {
+    static thread_local int cached_dev = -1, cus = 0;
+    int dev = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    if (dev != cached_dev) {
+        ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cached_dev = dev;
+    }
+    int per_cu = 0;
+    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dct_bf16<M>, 256, 0));
+    if (per_cu < 1) per_cu = 1;
+    const int64_t want = (int64_t(total_waves) + 3) / 4;
+    const int grid = int(std::min<int64_t>(want, int64_t(per_cu) * cus));
+    hipLaunchKernelGGL((k_dct_bf16<M>), dim3(grid), dim3(256), 0, s, a);
+    ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
+}
+
 template <int M>
 adct_status launch_dct_mode(const DctArgs &a, int total_waves, hipStream_t s) {
+    if (bf16_form(a) && (M != kDecode || a.coef_q)) return launch_dct_bf16<M>(a, total_waves, s);
     return a.r <= 16 ? launch_dct_kernel<M, true>(a, total_waves, s) : launch_dct_kernel<M, false>(a, total_waves, s);
 }
 

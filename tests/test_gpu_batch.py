@@ -61,6 +61,20 @@ def test_batch_schedules_agree(cuda, small_set, wgs, split):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("names,r_lo,r_hi", [
+    (["DCT", "T1", "T4"], 5, 20),            # the DCT's first coefficient window only
+    (["LO", "DCT", "T6"], 40, 64),           # the output range starts in the second window
+    (["DCT", "T2", "DCT"], 30, 34),          # the DCT twice, across the window edge
+    (["RDCT", "T1"], 1, 63),                 # integer transforms only (no DCT kernel)
+    (["DCT"], 1, 33),                        # the DCT only (no integer kernel)
+])
+def test_batch_lists_and_ranges(cuda, small_set, names, r_lo, r_hi):
+    base, planes = _pack(small_set, cuda)
+    sse = A.evaluate_batch(base, planes, names, r_lo, r_hi).cpu().numpy()
+    ref = OB.sse_table(small_set, names, r_lo, r_hi)
+    _check(sse, ref, names)
+
+
 def test_batch_graph_replays(cuda, small_set):
     import torch
     base, planes = _pack(small_set, cuda)

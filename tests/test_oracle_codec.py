@@ -55,6 +55,33 @@ def test_lossless_at_r64(img, name):
     np.testing.assert_allclose(res["real"], img, atol=1e-9)
 
 
+def test_dct_rational_coefficients_exact(img):
+    """forward_dct equals scipy's orthonormal DCT-II everywhere, and its four
+    rational coefficients equal the integer +-pixel sums over 8 exactly."""
+    blocks = Co.to_blocks(img)
+    b = Co.forward_dct(blocks)
+    np.testing.assert_allclose(b, dctn(blocks.astype(np.float64), type=2, norm="ortho", axes=(1, 2)),
+                               atol=1e-10)
+    s4 = np.array([1, -1, -1, 1, 1, -1, -1, 1])
+    a = blocks.astype(np.int64)
+    assert np.array_equal(b[:, 0, 0] * 8, a.sum(axis=(1, 2)))
+    assert np.array_equal(b[:, 4, 4] * 8, np.einsum("x,bxy,y->b", s4, a, s4))
+    assert np.array_equal(b[:, 0, 4] * 8, np.einsum("bxy,y->b", a, s4))
+    assert np.array_equal(b[:, 4, 0] * 8, np.einsum("x,bxy->b", s4, a))
+
+
+def test_dct_quantiser_tie_rounds_away_from_zero():
+    """A flat block of 3s has B(0,0) = 24 exactly; with step 16 that is 1.5
+    steps, which the quantiser rounds away from zero to 2 (32), so r = 1
+    reconstructs every pixel as 32 / 8 = 4."""
+    img = np.full((8, 8), 3, dtype=np.uint8)
+    res = Co.evaluate_dct(img, 1, 16)
+    assert res["coef_scaled"][0, 0] == 24.0
+    assert np.all(res["rec"] == 4)
+    res = Co.evaluate_dct(np.full((8, 8), 1, dtype=np.uint8), 1, 16)       # 8 / 16 = 0.5 -> 1
+    assert np.all(res["rec"] == 2)
+
+
 def test_dct_lossless_at_r64(img):
     assert Co.evaluate_dct(img, 64)["sse"] == 0
 
