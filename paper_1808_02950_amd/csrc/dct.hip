@@ -377,9 +377,11 @@ __device__ __forceinline__ void load_rows(const DctArgs &a, const DTile &T, int 
     px[1] = __builtin_nontemporal_load((const u32x2 *)(base + (off + uint32_t(P.pitch_in))));
 }
 
+// One 16-block tile; returns the lane's squared error of its block (evaluate),
+// or 0.
 template <int MODE>
-__device__ __forceinline__ void process_rows(const DctArgs &a, const DTile &T, const u32x2 (&px)[2],
-                                             const KOps &K, int g, int lane) {
+__device__ __forceinline__ uint32_t process_rows(const DctArgs &a, const DTile &T, const u32x2 (&px)[2],
+                                                 const KOps &K, int g) {
     const PlaneArg &P = a.pl[T.p];
     const int64_t cb = (int64_t(T.f) * a.blocks_per_frame + P.block_off + T.b) * a.r + 4 * g;
     const float step = float(a.step);
@@ -416,7 +418,7 @@ __device__ __forceinline__ void process_rows(const DctArgs &a, const DTile &T, c
         for (int i = 0; i < 4; ++i)
             bv[i] = (T.active && 4 * g + i < a.r) ? float(a.coef_q[cb + i]) * step : 0.f;
     }
-    if constexpr (MODE == kEncode) return;
+    if constexpr (MODE == kEncode) return 0u;
     const uint2 bhi = {pack_bf16(bv[0], bv[1]), pack_bf16(bv[2], bv[3])};
     uint2 blo = {0u, 0u};
     if constexpr (MODE == kDecode) {
@@ -456,19 +458,63 @@ __device__ __forceinline__ void process_rows(const DctArgs &a, const DTile &T, c
         __builtin_nontemporal_store(u32x2{w[0], w[1]}, (u32x2 *)(dbase + doff));
         __builtin_nontemporal_store(u32x2{w[2], w[3]}, (u32x2 *)(dbase + (doff + uint32_t(P.pitch_out))));
     }
-    if constexpr (MODE == kEvaluate) {
-        uint32_t sq = 0, cross = 0;
-        const uint32_t o[4] = {px[0].x, px[0].y, px[1].x, px[1].y};
+    if constexpr (MODE != kEvaluate) return 0u;
+    uint32_t sq = 0, cross = 0;
+    const uint32_t o[4] = {px[0].x, px[0].y, px[1].x, px[1].y};
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            sq = __builtin_amdgcn_udot4(w[t], w[t], sq, false);
-            sq = __builtin_amdgcn_udot4(o[t], o[t], sq, false);
-            cross = __builtin_amdgcn_udot4(w[t], o[t], cross, false);
+    for (int t = 0; t < 4; ++t) {
+        sq = __builtin_amdgcn_udot4(w[t], w[t], sq, false);
+        sq = __builtin_amdgcn_udot4(o[t], o[t], sq, false);
+        cross = __builtin_amdgcn_udot4(w[t], o[t], cross, false);
+    }
+    return T.active ? sq - 2u * cross : 0u;
+}
+
+// A wave takes 4 consecutive 16-block tiles per pass ("group"), loads all of
+// them (8 loads of 8 bytes per lane, 4 KB per wave) one group ahead, and adds
+// the squared errors of tiles of one (frame, plane) before one wave sum and one
+// atomic.
+constexpr int kGroup = 4;
+
+struct DGroup {
+    DTile t[kGroup];
+    bool live[kGroup];    // tile index inside the launch
+};
+
+__device__ __forceinline__ void group_of(const DctArgs &a, int grp, int total, int n, DGroup &G) {
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+        const int gw = grp * kGroup + q;
+        G.live[q] = gw < total;
+        G.t[q] = dtile_of(a, G.live[q] ? gw : total - 1, n);
+    }
+}
+
+__device__ __forceinline__ void load_group(const DctArgs &a, const DGroup &G, int g, u32x2 (&px)[kGroup][2]) {
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) load_rows(a, G.t[q], g, px[q]);
+}
+
+template <int MODE>
+__device__ __forceinline__ void process_group(const DctArgs &a, const DGroup &G, const u32x2 (&px)[kGroup][2],
+                                              const KOps &K, int g, int lane) {
+    uint32_t e = 0;
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+        if (G.live[q]) e += process_rows<MODE>(a, G.t[q], px[q], K, g);
+        if constexpr (MODE == kEvaluate) {
+            const bool last = q + 1 == kGroup || !G.live[q + 1 < kGroup ? q + 1 : q] ||
+                              G.t[q + 1 < kGroup ? q + 1 : q].f != G.t[q].f ||
+                              G.t[q + 1 < kGroup ? q + 1 : q].p != G.t[q].p;
+            if (last && G.live[q]) {                        // wave-uniform
+                uint32_t s = e;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+                if (lane == 0 && s)
+                    atomicAdd(a.sse + int64_t(G.t[q].f) * a.n_planes + G.t[q].p, (unsigned long long)s);
+                e = 0;
+            }
         }
-        unsigned e = T.active ? sq - 2u * cross : 0u;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-        if (lane == 0 && e) atomicAdd(a.sse + int64_t(T.f) * a.n_planes + T.p, (unsigned long long)e);
     }
 }
 
@@ -477,31 +523,33 @@ __global__ __launch_bounds__(256) void k_dct_bf16(const DctArgs a) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int total = a.n_frames * a.waves_per_frame;
+    const int groups = (total + kGroup - 1) / kGroup;
     const int stride = int(gridDim.x) * 4;
-    int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    if (gw >= total) return;                                // whole wave leaves
+    int gi = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (gi >= groups) return;                               // whole wave leaves
     KOps K;
     make_kops(a, lane, K);
-    u32x2 pa[2] = {}, pb[2] = {};
-    DTile ta = dtile_of(a, gw, n), tb = ta;
-    if constexpr (MODE != kDecode) load_rows(a, ta, g, pa);
-    // the next loads are issued on every pass (a wave's last pass re-reads its
-    // current tile), as in the float32 form
+    u32x2 pa[kGroup][2] = {}, pb[kGroup][2] = {};
+    DGroup ga, gb;
+    group_of(a, gi, total, n, ga);
+    if constexpr (MODE != kDecode) load_group(a, ga, g, pa);
+    // the next group's loads are issued on every pass (a wave's last pass
+    // re-reads its current group)
     while (true) {
-        int nxt = gw + stride;
-        bool more = nxt < total;                            // wave-uniform
-        tb = dtile_of(a, more ? nxt : gw, n);
-        if constexpr (MODE != kDecode) load_rows(a, tb, g, pb);
-        process_rows<MODE>(a, ta, pa, K, g, lane);
+        int nxt = gi + stride;
+        bool more = nxt < groups;                           // wave-uniform
+        group_of(a, more ? nxt : gi, total, n, gb);
+        if constexpr (MODE != kDecode) load_group(a, gb, g, pb);
+        process_group<MODE>(a, ga, pa, K, g, lane);
         if (!more) break;
-        gw = nxt;
-        nxt = gw + stride;
-        more = nxt < total;
-        ta = dtile_of(a, more ? nxt : gw, n);
-        if constexpr (MODE != kDecode) load_rows(a, ta, g, pa);
-        process_rows<MODE>(a, tb, pb, K, g, lane);
+        gi = nxt;
+        nxt = gi + stride;
+        more = nxt < groups;
+        group_of(a, more ? nxt : gi, total, n, ga);
+        if constexpr (MODE != kDecode) load_group(a, ga, g, pa);
+        process_group<MODE>(a, gb, pb, K, g, lane);
         if (!more) break;
-        gw = nxt;
+        gi = nxt;
     }
 }
 
@@ -543,7 +591,8 @@ adct_status launch_dct_bf16(const DctArgs &a, int total_waves, hipStream_t s) {
     int per_cu = 0;
     ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dct_bf16<M>, 256, 0));
     if (per_cu < 1) per_cu = 1;
-    const int64_t want = (int64_t(total_waves) + 3) / 4;
+    const int64_t groups = (int64_t(total_waves) + kGroup - 1) / kGroup;
+    const int64_t want = (groups + 3) / 4;
     const int grid = int(std::min<int64_t>(want, int64_t(per_cu) * cus));
     hipLaunchKernelGGL((k_dct_bf16<M>), dim3(grid), dim3(256), 0, s, a);
     ADCT_HIP(hipGetLastError());
