@@ -44,6 +44,16 @@ __device__ __forceinline__ int inv_addr(int p, int c) {
     return grp * 64 + ((c & 15) >> 2) * 16 + (p & 15);
 }
 
+// K[c][p] = C[k][x] C[l][y] as a float32 product, except for (k, l) in
+// {0, 4}^2: there a_0 = 1/sqrt(8) and a_4 cos((2n+1) pi / 4) = +-1/sqrt(8), so
+// every entry is exactly +-1/8.  Using the exact value keeps those four
+// coefficients exact sums over 8, so their quantiser ties (B / step exactly
+// half a step) are decided as the quantiser defines them.
+__device__ __forceinline__ float k_entry(const DctArgs &a, int k, int l, int x, int y) {
+    const float v = a.C[8 * k + x] * a.C[8 * l + y];
+    return ((k & 3) == 0 && (l & 3) == 0) ? copysignf(0.125f, v) : v;
+}
+
 struct DTile {
     int f, p, b;
     bool active;
@@ -212,7 +222,7 @@ __global__ __launch_bounds__(256) void k_dct(const DctArgs a) {
     for (int i = threadIdx.x; i < 64 * 64; i += 256) {
         const int c = i >> 6, p = i & 63;
         const int kc = kZZ[c] >> 3, lc = kZZ[c] & 7;
-        const float v = a.C[8 * kc + (p >> 3)] * a.C[8 * lc + (p & 7)];
+        const float v = k_entry(a, kc, lc, p >> 3, p & 7);
         kf[fwd_addr(c, p)] = v;
         ki[inv_addr(p, c)] = v;
     }
@@ -341,7 +351,7 @@ __device__ __forceinline__ void make_kops(const DctArgs &a, int lane, KOps &K) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 uint32_t t[3];
-                split3(a.C[8 * kc + 2 * g + h] * a.C[8 * lc + j], t);
+                split3(k_entry(a, kc, lc, 2 * g + h, j), t);
 #pragma unroll
                 for (int s = 0; s < 3; ++s) e[s][j] = t[s];
             }
@@ -359,7 +369,7 @@ __device__ __forceinline__ void make_kops(const DctArgs &a, int lane, KOps &K) {
         for (int i = 0; i < 4; ++i) {
             const int z = 4 * g + i, kc = kZZ[z] >> 3, lc = kZZ[z] & 7;
             uint32_t tt[3];
-            split3(a.C[8 * kc + x] * a.C[8 * lc + y], tt);
+            split3(k_entry(a, kc, lc, x, y), tt);
 #pragma unroll
             for (int s = 0; s < 3; ++s) e[s][i] = tt[s];
         }

@@ -75,6 +75,30 @@ def test_dct_quantised(cuda):
     assert np.array_equal(rec2.cpu().numpy(), recon.cpu().numpy())
 
 
+@pytest.mark.parametrize("r,step", [(10, 12), (20, 16), (16, 8), (10, 32)])
+def test_dct_quantised_forms(cuda, r, step):
+    """Both arithmetic forms (three-term bfloat16 split for r <= 16 with a
+    power-of-two step >= 8, float32 products otherwise) against the float64
+    oracle: every level equal except where B / step is within float32 noise of
+    a half on an irrational coefficient; the rational ones (exact sums over 8)
+    must match at their exact ties too."""
+    import torch
+    img = ar1_image(128, 256, 0.95, seed=31 + r + step)
+    ref = Co.evaluate_dct(img, r, step=step)
+    d = _dev(img, cuda)
+    ci, _ = A.encode_blocks(d, "DCT", r, step, want_int=True, want_scaled=True)
+    q = ci.cpu().numpy().astype(np.int64)
+    x = ref["coef_scaled"] / step
+    qref = (np.sign(x) * np.floor(np.abs(x) + 0.5)).astype(np.int64)
+    near = np.abs(np.abs(x) - np.floor(np.abs(x)) - 0.5) < 1e-4
+    zz = [(k, l) for k, l in Co.zigzag()][:r]
+    rational = np.array([k in (0, 4) and l in (0, 4) for k, l in zz])
+    assert not np.any((q != qref) & (~near | rational[None, :]))
+    recon = torch.empty_like(d)
+    ev = A.evaluate_coding(d, "DCT", r, step, recon=recon)
+    assert abs(ev.psnr - ref["psnr"]) <= 1e-5 * ref["psnr"]
+
+
 def test_dct_stream(cuda):
     spec = video_spec(n_frames=2, width=144, height=80, seed=3)
     bases = video_base_planes(spec)
