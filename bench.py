@@ -151,7 +151,7 @@ def batch_row():
         "mean_psnr_r10": {n: round(float(psnr[t, 9]), 4) for t, n in enumerate(names)}}}
 
 
-FILTER_FLOP_PER_PX = 2 * (9 + 288 * 32 + 288)     # 19,584: forward, per output pixel
+FILTER_FLOP_PER_PX = 2 * (9 * 32 + 288 * 32 + 288)   # 19,584: forward MACs x 2, per output pixel
 
 
 def filter_images(n_train: int, n_val: int):
