@@ -2,7 +2,10 @@
 // the paper), batched on the GPU.
 //
 // The search space D = P^8 (Sec. 3.2) is enumerated once into a device table
-// (packed int8 vectors, squared norms, cosines to the eight DCT rows).  The
+// (packed int8 vectors, primitive flags); a candidate's cosine to
+// a DCT row is recomputed where it is needed (one float64 dot product of eight
+// terms and the candidate's inverse norm: cheaper than reading 64 bytes of
+// stored cosines per candidate, and always the same value).  The
 // greedy problem of Eq. (6) is then answered query by query: a query is (rows
 // already chosen, DCT row to approximate); the device finds the largest cosine
 // (smallest angle, Sec. 3.3) among candidates orthogonal to every chosen row
@@ -55,6 +58,26 @@ __device__ __forceinline__ int sdot8(uint2 a, uint2 b) {
                                   false);
 }
 
+__device__ __forceinline__ void unpack8(uint2 p, int (&v)[8]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] = int(int8_t(uint8_t(p.x >> (8 * e))));
+        v[4 + e] = int(int8_t(uint8_t(p.y >> (8 * e))));
+    }
+}
+
+// 1 / |v| in float64 (|v|^2 is an exact integer)
+__device__ __forceinline__ double inv_norm(uint2 p) { return 1.0 / sqrt(double(sdot8(p, p))); }
+
+// cos of the angle between v and DCT row r: the float64 dot product in entry
+// order, times 1 / |v| (the DCT rows have unit norm)
+__device__ __forceinline__ double cos_row(const int (&v)[8], double inv, const DctRows &rows, int r) {
+    double dot = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dot = fma(double(v[e]), rows.c[8 * r + e], dot);
+    return dot * inv;
+}
+
 // monotone map of a double onto uint64 (for atomicMax)
 __device__ __forceinline__ unsigned long long order_key(double x) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(x);
@@ -67,8 +90,7 @@ __host__ __device__ __forceinline__ double key_value(unsigned long long k) {
 
 // ------------------------------------------------------------ enumeration
 
-__global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, int *norm2, double *cosv,
-                       uint8_t *prim, DctRows rows) {
+__global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, uint8_t *prim) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t idx = i + 1;                             // canonical index; 0 is the zero vector
@@ -78,26 +100,17 @@ __global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, int *norm2, doub
         idx /= b;
     }
     uint32_t lo = 0, hi = 0;
-    int s = 0;
     bool odd = false, non3 = false;
     for (int e = 0; e < 8; ++e) {
         const uint32_t byte = uint32_t(uint8_t(int8_t(v[e])));
         if (e < 4) lo |= byte << (8 * e); else hi |= byte << (8 * (e - 4));
-        s += v[e] * v[e];
         odd |= (v[e] & 1) != 0;
         non3 |= (v[e] % 3) != 0;
     }
     vec[i] = make_uint2(lo, hi);
-    norm2[i] = s;
     // gcd of the entries is 1 exactly when some entry is odd and some entry is
     // not a multiple of 3 (entries are within +-4)
     prim[i] = uint8_t(odd && non3);
-    const double inv = 1.0 / sqrt(double(s));
-    for (int r = 0; r < 8; ++r) {
-        double dot = 0.0;
-        for (int e = 0; e < 8; ++e) dot = fma(double(v[e]), rows.c[8 * r + e], dot);
-        cosv[i * 8 + r] = dot * inv;
-    }
 }
 
 // ------------------------------------------------------------ greedy queries
@@ -115,19 +128,24 @@ __device__ __forceinline__ bool feasible(const Query &q, uint2 v) {
 }
 
 __global__ __launch_bounds__(256) void k_qmax(const Query *qs, int64_t n, const uint2 *vec,
-                                             const double *cosv, unsigned long long *best) {
+                                             const DctRows rows, unsigned long long *best) {
     const Query q = qs[blockIdx.y];
     double m = -2.0;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
-        if (feasible(q, vec[i])) m = fmax(m, cosv[i * 8 + q.row]);
+        const uint2 p = vec[i];
+        if (feasible(q, p)) {
+            int v[8];
+            unpack8(p, v);
+            m = fmax(m, cos_row(v, inv_norm(p), rows, q.row));
+        }
     }
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0 && m > -2.0) atomicMax(best + blockIdx.y, order_key(m));
 }
 
 __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, int64_t n, const uint2 *vec,
-                                                 const double *cosv, const unsigned long long *best,
+                                                 const DctRows rows, const unsigned long long *best,
                                                  int cap, int64_t *out_idx, double *out_cos,
                                                  int *count) {
     const int qi = blockIdx.y;
@@ -136,8 +154,12 @@ __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, int64_t n, co
     const double lo = key_value(best[qi]) - kWindow;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
-        const double c = cosv[i * 8 + q.row];
-        if (c >= lo && feasible(q, vec[i])) {
+        const uint2 p = vec[i];
+        if (!feasible(q, p)) continue;
+        int v[8];
+        unpack8(p, v);
+        const double c = cos_row(v, inv_norm(p), rows, q.row);
+        if (c >= lo) {
             const int pos = atomicAdd(count + qi, 1);
             if (pos < cap) {
                 out_idx[int64_t(qi) * cap + pos] = i;
@@ -149,23 +171,64 @@ __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, int64_t n, co
 
 // ------------------------------------------------------------ top-k scan
 
+// Bin edges of the angle histogram: 8 bins per octave of u = 1 - cos.  With
+// u = (1 + f) 2^e, -8 log2 u = -8 e - 8 log2(1 + f), and 8 log2(1 + f) passes an
+// integer i where 1 + f passes 2^(i/8); kOctFrac[i] holds the 52 fraction bits
+// of 2^(i/8).  The histogram and the collection use the same edges, and the host
+// ranks the collected candidates exactly, so the edges need only be fixed and
+// monotone.
+struct OctFrac {
+    unsigned long long f[8];
+};
+constexpr double csqrt(double a) {
+    double x = a;
+    for (int i = 0; i < 64; ++i) x = 0.5 * (x + a / x);
+    return x;
+}
+constexpr OctFrac make_oct_frac() {
+    OctFrac t{};
+    const double r8 = csqrt(csqrt(csqrt(2.0)));           // 2^(1/8)
+    double x = 1.0;
+    for (int i = 0; i < 8; ++i) {
+        t.f[i] = (unsigned long long)((x - 1.0) * 4503599627370496.0);   // (2^(i/8) - 1) 2^52
+        x *= r8;
+    }
+    return t;
+}
+__device__ constexpr OctFrac kOctFrac = make_oct_frac();
+
+// floor(-8 log2(1 - c)) truncated toward zero (so angles past 90 degrees give
+// -1 or 0), clamped to the last bin; c >= 1 is the last bin
 __device__ __forceinline__ int angle_bin(double c) {
-    const double u = 1.0 - c;                                   // >= 0 up to rounding
+    const double u = 1.0 - c;
     if (!(u > 0.0)) return kHistBins - 1;
-    const int b = int(-log2(u) * 8.0);
-    return b < 0 ? -1 : (b >= kHistBins ? kHistBins - 1 : b);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(u);
+    const int e = int((bits >> 52) & 0x7ffu) - 1023;     // u >= 2^-53 is normal
+    const unsigned long long f = bits & 0xfffffffffffffull;
+    int j = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) j += f >= kOctFrac.f[i] ? 1 : 0;
+    int b;
+    if (e < 0) b = -8 * e - (f != 0 ? j + 1 : 0);      // positive: floor
+    else b = (e == 0 && j == 0) ? 0 : -1;              // u in [1, 2]: -8 log2 u in [-8, 0]
+    return b >= kHistBins ? kHistBins - 1 : b;
 }
 
-__global__ __launch_bounds__(256) void k_hist(int64_t n, const double *cosv, const uint8_t *prim,
-                                             int primitive, unsigned *hist) {
+__global__ __launch_bounds__(256) void k_hist(int64_t n, const uint2 *vec, const uint8_t *prim, int primitive,
+                                             const DctRows rows, unsigned *hist) {
     __shared__ unsigned h[8 * kHistBins];
     for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
         if (primitive && !prim[i]) continue;
+        const uint2 p = vec[i];
+        int v[8];
+        unpack8(p, v);
+        const double inv = inv_norm(p);
+#pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int bn = angle_bin(cosv[i * 8 + r]);
+            const int bn = angle_bin(cos_row(v, inv, rows, r));
             if (bn >= 0) atomicAdd(&h[r * kHistBins + bn], 1u);
         }
     }
@@ -180,14 +243,20 @@ struct Thresholds {
     int64_t off[8];
 };
 
-__global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const double *cosv, const uint8_t *prim,
-                                                     int primitive, Thresholds th, int64_t *out_idx,
-                                                     double *out_cos, unsigned long long *count) {
+__global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const uint2 *vec, const uint8_t *prim,
+                                                     int primitive, const DctRows rows, Thresholds th,
+                                                     int64_t *out_idx, double *out_cos,
+                                                     unsigned long long *count) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
         if (primitive && !prim[i]) continue;
+        const uint2 p = vec[i];
+        int v[8];
+        unpack8(p, v);
+        const double inv = inv_norm(p);
+#pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const double c = cosv[i * 8 + r];
+            const double c = cos_row(v, inv, rows, r);
             if (angle_bin(c) >= th.bin[r]) {
                 const unsigned long long pos = atomicAdd(count + r, 1ull);
                 if (int64_t(pos) < th.cap[r]) {
@@ -242,7 +311,7 @@ struct Space {
     int b = 0;
     int8_t digits[9] = {};
     int64_t n = 0;
-    DevBuf vec, norm2, cosv, prim;
+    DevBuf vec, prim;
 };
 
 adct_status canonical_digits(const int8_t *P, int nP, int8_t *out, int *b) {
@@ -272,16 +341,13 @@ adct_status build_space(const int8_t *P, int nP, Space &sp, hipStream_t s) {
     sp.n = total - 1;
     if (sp.n < 1) return fail(ADCT_ERANGE, "search space is empty");
     if ((st = dalloc<uint2>(sp.vec, sp.n))) return st;
-    if ((st = dalloc<int>(sp.norm2, sp.n))) return st;
-    if ((st = dalloc<double>(sp.cosv, sp.n * 8))) return st;
     if ((st = dalloc<uint8_t>(sp.prim, sp.n))) return st;
     Digits dg;
     memset(&dg, 0, sizeof(dg));
     for (int i = 0; i < sp.b; ++i) dg.d[i] = sp.digits[i];
     const int64_t blocks = (sp.n + 255) / 256;
     hipLaunchKernelGGL(k_enum, dim3(unsigned(blocks)), dim3(256), 0, s, sp.b, dg, sp.n,
-                       (uint2 *)sp.vec.p, (int *)sp.norm2.p, (double *)sp.cosv.p, (uint8_t *)sp.prim.p,
-                       dct_rows());
+                       (uint2 *)sp.vec.p, (uint8_t *)sp.prim.p);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }
@@ -388,8 +454,7 @@ adct_status run_queries(const Space &sp, const std::vector<Query> &qs,
     for (int y0 = 0; y0 < nq; y0 += 65535) {
         const int ny = std::min(nq - y0, 65535);
         hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, sp.n,
-                           (const uint2 *)sp.vec.p, (const double *)sp.cosv.p,
-                           (unsigned long long *)dbest.p + y0);
+                           (const uint2 *)sp.vec.p, dct_rows(), (unsigned long long *)dbest.p + y0);
         ADCT_HIP(hipGetLastError());
     }
     for (;;) {
@@ -400,7 +465,7 @@ adct_status run_queries(const Space &sp, const std::vector<Query> &qs,
         for (int y0 = 0; y0 < nq; y0 += 65535) {
             const int ny = std::min(nq - y0, 65535);
             hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0,
-                               sp.n, (const uint2 *)sp.vec.p, (const double *)sp.cosv.p,
+                               sp.n, (const uint2 *)sp.vec.p, dct_rows(),
                                (const unsigned long long *)dbest.p + y0, cap,
                                (int64_t *)didx.p + int64_t(y0) * cap, (double *)dcos.p + int64_t(y0) * cap,
                                (int *)dcount.p + y0);
@@ -610,8 +675,8 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     if ((st = dalloc<unsigned>(dhist, 8 * kHistBins))) return st;
     ADCT_HIP(hipMemsetAsync(dhist.p, 0, sizeof(unsigned) * 8 * kHistBins, s));
     const unsigned grid = unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048));
-    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), 0, s, sp.n, (const double *)sp.cosv.p,
-                       (const uint8_t *)sp.prim.p, primitive, (unsigned *)dhist.p);
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec.p,
+                       (const uint8_t *)sp.prim.p, primitive, dct_rows(), (unsigned *)dhist.p);
     ADCT_HIP(hipGetLastError());
     std::vector<unsigned> hist(8 * kHistBins);
     ADCT_HIP(hipMemcpyAsync(hist.data(), dhist.p, sizeof(unsigned) * hist.size(), hipMemcpyDeviceToHost, s));
@@ -638,9 +703,9 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     if ((st = dalloc<double>(dcos, total))) return st;
     if ((st = dalloc<unsigned long long>(dcnt, 8))) return st;
     ADCT_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(unsigned long long) * 8, s));
-    hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const double *)sp.cosv.p,
-                       (const uint8_t *)sp.prim.p, primitive, th, (int64_t *)didx.p, (double *)dcos.p,
-                       (unsigned long long *)dcnt.p);
+    hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec.p,
+                       (const uint8_t *)sp.prim.p, primitive, dct_rows(), th, (int64_t *)didx.p,
+                       (double *)dcos.p, (unsigned long long *)dcnt.p);
     ADCT_HIP(hipGetLastError());
     std::vector<int64_t> idx(std::max<int64_t>(total, 1));
     std::vector<double> cs(std::max<int64_t>(total, 1));
