@@ -15,6 +15,7 @@ Modules
   measures  error energy, MSE, coding gain, transform efficiency, circular statistics
   batch     SSE table over images x transforms x retention levels
   postfilter  float64 conv network forward/backward on bfloat16-rounded operands
+  ssim      structural similarity of a reconstruction (Gaussian-window local statistics)
 
 Every function cites the passage of the paper it restates.  Readings taken where
 the paper is silent or ambiguous are stated where they are used.
