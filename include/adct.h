@@ -160,6 +160,26 @@ adct_status adct_evaluate_coding(const uint8_t *img, int H, int W, int pitch,
                                  uint64_t *sse_dev, double *mse_host, double *psnr_host,
                                  adct_stream_t stream);
 
+/* Structural similarity of `test` against `ref` (Sec. 6.1.1 names SSIM as its
+ * third figure of merit and cites its definition): for every plane of every
+ * frame, the mean over all positions where an 11 x 11 Gaussian window
+ * (sigma 1.5, unit sum) fits inside the plane of
+ *   ((2 mu_r mu_t + C1)(2 s_rt + C2)) / ((mu_r^2 + mu_t^2 + C1)(s_r^2 + s_t^2 + C2)),
+ * C1 = (0.01 * 255)^2, C2 = (0.03 * 255)^2, with the window-weighted means,
+ * variances and covariance; no padding, no downsampling.  Frame f of each
+ * buffer starts at ref + f * frame_stride_ref (resp. test + f *
+ * frame_stride_test), device memory; planes[p] (host array, n_planes <= 4)
+ * gives offset, H, W and pitch, the same for both buffers.  ssim_out: device
+ * float64 [n_frames][n_planes], 8-byte aligned, overwritten.  Float64
+ * arithmetic; each plane's result does not depend on the launch order.
+ * Errors: ADCT_EINVAL null pointer; ADCT_ERANGE n_frames < 1, n_planes not in
+ * [1, 4], a plane above 2^26 pixels; ADCT_EDIM a plane smaller than 11 x 11,
+ * pitch < W, negative offset, unaligned ssim_out, non-positive frame stride
+ * with several frames. */
+adct_status adct_ssim(const uint8_t *ref, int64_t frame_stride_ref, const uint8_t *test,
+                      int64_t frame_stride_test, int n_frames, const adct_plane *planes, int n_planes,
+                      double *ssim_out, adct_stream_t stream);
+
 /* Fused encode + decode + error over a stream of frames in ONE launch.
  * Frame f starts at frames + f * frame_stride (device); plane p of it is
  * planes[p] (host array, n_planes <= 4).  Coefficients go to

@@ -64,6 +64,7 @@ _SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_double), _P]),
     "adct_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I,
                                   ctypes.POINTER(Matrix), _I, _I, _P, _P, _I64, _P, _P]),
+    "adct_ssim": (_I, [_P, _I64, _P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _P]),
     "adct_derive_transform": (_I, [_P, _I, _I, _P, _I, _I, ctypes.POINTER(Matrix), _I,
                                    ctypes.POINTER(_I), _P, ctypes.POINTER(_I64),
                                    ctypes.POINTER(_I64), _P]),
@@ -249,6 +250,32 @@ def evaluate_stream(frames, planes, t, r: int, quant_step: int = 0, coef=None, r
                                       recon.stride(0) if recon is not None else 0,
                                       _ptr(sse), _stream(stream)))
     return sse
+
+
+def ssim(ref, test, planes, out=None, stream=None):
+    """adct_ssim: mean SSIM of every plane of every frame of `test` against `ref`.
+    With planes (a list of (offset, H, W, pitch)) the inputs are uint8 CUDA
+    tensors (n_frames, frame_bytes); with planes=None they are two 2-D images
+    (one frame, one plane).  Returns the device float64 tensor
+    (n_frames, n_planes); does not synchronise."""
+    import torch
+    _need_cuda(ref, torch.uint8, "ref")
+    _need_cuda(test, torch.uint8, "test")
+    if planes is None:
+        if ref.dim() != 2 or ref.shape != test.shape or test.stride(0) != ref.stride(0):
+            raise ValueError("two 2-D images of one shape and pitch are required")
+        planes = [(0, ref.shape[0], ref.shape[1], ref.stride(0))]
+        nf, fs_r, fs_t = 1, 0, 0
+    else:
+        nf, fs_r, fs_t = ref.shape[0], ref.stride(0), test.stride(0)
+    if test.shape[0] != ref.shape[0]:
+        raise ValueError("ref and test need the same number of frames")
+    if out is None:
+        out = torch.empty((nf, len(planes)), dtype=torch.float64, device=ref.device)
+    arr = planes_struct(planes)
+    _check(lib().adct_ssim(_ptr(ref), fs_r, _ptr(test), fs_t, nf, arr, len(planes), _ptr(out),
+                           _stream(stream)))
+    return out
 
 
 def stream_blocks_per_frame(planes) -> int:

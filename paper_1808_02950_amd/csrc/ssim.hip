@@ -1,0 +1,224 @@
+// Structural similarity (SSIM) of a reconstruction against its original, the
+// third figure of merit of Sec. 6.1.1, with the definition of the reference it
+// cites: local weighted statistics over an 11 x 11 Gaussian window (sigma 1.5,
+// unit sum) at every position where the window fits, C1 = (0.01 * 255)^2,
+// C2 = (0.03 * 255)^2, and the mean of the map per plane.
+//
+// One wave computes a tile of the map: 64 output columns (one per lane) x 88
+// output rows.  Input rows stream through it once: each row's two pixels per
+// position go to a per-wave LDS row (x | y << 16), every lane sums its 11
+// horizontal neighbours' x, y, x^2, y^2, xy with the 1-D weights, and that row
+// of horizontal sums is folded into the 11 output rows it reaches with the
+// vertical weights.  Eleven rotating accumulators hold those rows; with the row
+// loop unrolled by 11 every accumulator index is a compile-time constant.  An
+// accumulator is complete when its last input row arrives: the lane then
+// evaluates SSIM there.  Pixels are centred at 128 before the products (the
+// variances and covariance do not change) and everything accumulates in
+// float64.  Each plane's map sum is accumulated as a 2^-36 fixed-point 64-bit
+// integer, so the per-plane result does not depend on the order of the tiles.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "adct_internal.hpp"
+
+namespace adct {
+namespace {
+
+constexpr int kWin = 11;
+constexpr int kTileRows = 88;                 // output rows per tile (a multiple of 11)
+constexpr double kC1 = 6.5025;                // (0.01 * 255)^2
+constexpr double kC2 = 58.5225;               // (0.03 * 255)^2
+constexpr double kFix = 68719476736.0;        // 2^36
+
+struct SsimPlane {
+    int64_t off;
+    int32_t pitch, H, W;
+    int32_t strips, tile_start;               // 64-column strips; first tile of the plane in a frame
+};
+
+struct SsimArgs {
+    const uint8_t *ref;
+    const uint8_t *test;
+    int64_t fs_ref, fs_test;
+    unsigned long long *acc;                  // [frame][plane] fixed-point map sums, then means
+    int32_t n_frames, n_planes, tiles_per_frame, pad;
+    SsimPlane pl[kMaxPlanes];
+    double w[kWin];                           // 1-D Gaussian weights, unit sum
+};
+
+// SSIM at one position from the window's sums of x, y, x^2, y^2, xy (pixels
+// centred at 128)
+__device__ __forceinline__ double ssim_at(const double (&s)[5]) {
+    const double mx = s[0], my = s[1];
+    const double vx = s[2] - mx * mx, vy = s[3] - my * my, cxy = s[4] - mx * my;
+    const double ux = mx + 128.0, uy = my + 128.0;
+    return ((2.0 * ux * uy + kC1) * (2.0 * cxy + kC2)) / ((ux * ux + uy * uy + kC1) * (vx + vy + kC2));
+}
+
+// one input row (relative index i = i0 + U) of the tile; U is the row's
+// position in its group of 11, so every accumulator slot is a constant
+template <int U>
+__device__ __forceinline__ void ssim_row(const SsimArgs &a, const uint8_t *rb, const uint8_t *tb, const SsimPlane &P,
+                                         int r0, int i0, int nout, int ca, int cb, int lane, uint32_t *row,
+                                         double (&acc)[kWin][5], double &sum, bool col_ok) {
+    const int i = i0 + U;
+    if (i >= nout + kWin - 1) return;                          // wave-uniform
+    const int64_t base = int64_t(std::min(r0 + i, P.H - 1)) * P.pitch;
+    row[lane] = uint32_t(rb[base + ca]) | (uint32_t(tb[base + ca]) << 16);
+    if (lane < kWin - 1) row[64 + lane] = uint32_t(rb[base + cb]) | (uint32_t(tb[base + cb]) << 16);
+    __builtin_amdgcn_wave_barrier();
+    double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < kWin; ++b) {
+        const uint32_t v = row[lane + b];
+        const int x = int(v & 0xffffu) - 128, y = int(v >> 16) - 128;
+        const double wb = a.w[b];
+        h[0] = fma(wb, double(x), h[0]);
+        h[1] = fma(wb, double(y), h[1]);
+        h[2] = fma(wb, double(x * x), h[2]);
+        h[3] = fma(wb, double(y * y), h[3]);
+        h[4] = fma(wb, double(x * y), h[4]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // this row feeds output rows o = i - d, d = 0..10, of slot (U - d) mod 11
+#pragma unroll
+    for (int d = 0; d < kWin; ++d) {
+        if (d <= i && i - d < nout) {
+            double(&s)[5] = acc[(U - d + kWin) % kWin];
+            const double wd = a.w[d];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) s[q] = fma(wd, h[q], s[q]);
+        }
+    }
+    // output row o = i - 10 is complete
+    if (i >= kWin - 1 && i - (kWin - 1) < nout) {
+        double(&s)[5] = acc[(U + 1) % kWin];
+        if (col_ok) sum += ssim_at(s);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s[q] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ssim(const SsimArgs a) {
+    __shared__ uint32_t rows[4][64 + kWin - 1];
+    const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
+    const int gw = int(blockIdx.x) * 4 + wave;
+    if (gw >= a.n_frames * a.tiles_per_frame) return;          // whole wave leaves
+    const int f = gw / a.tiles_per_frame;
+    int t = gw - f * a.tiles_per_frame;
+    int p = 0;
+    while (p + 1 < a.n_planes && t >= a.pl[p + 1].tile_start) ++p;
+    const SsimPlane &P = a.pl[p];
+    t -= P.tile_start;
+    const int band = t / P.strips, strip = t - band * P.strips;
+    const int OH = P.H - (kWin - 1), OW = P.W - (kWin - 1);
+    const int c0 = strip * 64, r0 = band * kTileRows;
+    const int nout = std::min(kTileRows, OH - r0);
+    const bool col_ok = c0 + lane < OW;
+    // input columns of this lane (and, for lanes 0..9, of the 10 columns past
+    // the strip), clamped into the plane: a clamped column only feeds outputs
+    // outside the map
+    const int ca = std::min(c0 + lane, P.W - 1), cb = std::min(c0 + 64 + lane, P.W - 1);
+    const uint8_t *rb = a.ref + int64_t(f) * a.fs_ref + P.off;
+    const uint8_t *tb = a.test + int64_t(f) * a.fs_test + P.off;
+    uint32_t *row = rows[wave];
+    double acc[kWin][5];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[k][q] = 0.0;
+    double sum = 0.0;
+    for (int i0 = 0; i0 < nout + kWin - 1; i0 += kWin) {
+        ssim_row<0>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<1>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<2>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<3>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<4>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<5>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<6>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<7>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<8>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<9>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<10>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+    }
+    // fixed point (|map| <= 1, at most 88 entries per lane), then the wave sum
+    long long v = llrint(sum * kFix);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) atomicAdd(a.acc + int64_t(f) * a.n_planes + p, (unsigned long long)v);
+}
+
+__global__ void k_ssim_zero(unsigned long long *acc, int n) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) acc[i] = 0ull;
+}
+
+// fixed-point map sums -> mean SSIM per (frame, plane), in place
+__global__ void k_ssim_final(unsigned long long *acc, int n_frames, int n_planes, SsimArgs a) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n_frames * n_planes) return;
+    const SsimPlane &P = a.pl[i % n_planes];
+    const double count = double(P.H - (kWin - 1)) * double(P.W - (kWin - 1));
+    const double mean = double((long long)acc[i]) / kFix / count;
+    acc[i] = (unsigned long long)__double_as_longlong(mean);
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+extern "C" adct_status adct_ssim(const uint8_t *ref, int64_t frame_stride_ref, const uint8_t *test,
+                                 int64_t frame_stride_test, int n_frames, const adct_plane *planes,
+                                 int n_planes, double *ssim_out, adct_stream_t stream) {
+    if (!ref || !test || !planes || !ssim_out) return fail(ADCT_EINVAL, "ref, test, planes and ssim_out are required");
+    if (n_frames < 1) return fail(ADCT_ERANGE, "n_frames must be >= 1");
+    if (n_planes < 1 || n_planes > kMaxPlanes) return fail(ADCT_ERANGE, "n_planes must be in [1, 4]");
+    if (reinterpret_cast<uintptr_t>(ssim_out) & 7) return fail(ADCT_EDIM, "ssim_out must be 8-byte aligned");
+    if (n_frames > 1 && (frame_stride_ref <= 0 || frame_stride_test <= 0))
+        return fail(ADCT_EDIM, "frame strides must be positive for several frames");
+    SsimArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ref = ref;
+    a.test = test;
+    a.fs_ref = frame_stride_ref;
+    a.fs_test = frame_stride_test;
+    a.acc = reinterpret_cast<unsigned long long *>(ssim_out);
+    a.n_frames = n_frames;
+    a.n_planes = n_planes;
+    int64_t tiles = 0;
+    for (int p = 0; p < n_planes; ++p) {
+        const adct_plane &q = planes[p];
+        if (q.H < kWin || q.W < kWin || q.pitch < q.W || q.offset < 0)
+            return fail(ADCT_EDIM, "each plane needs H, W >= 11, pitch >= W and offset >= 0");
+        if (int64_t(q.H) * q.W > (int64_t(1) << 26))
+            return fail(ADCT_ERANGE, "planes are limited to 2^26 pixels (fixed-point sum range)");
+        SsimPlane &d = a.pl[p];
+        d.off = q.offset;
+        d.pitch = q.pitch;
+        d.H = q.H;
+        d.W = q.W;
+        d.strips = (q.W - (kWin - 1) + 63) / 64;
+        d.tile_start = int32_t(tiles);
+        tiles += int64_t(d.strips) * ((q.H - (kWin - 1) + kTileRows - 1) / kTileRows);
+    }
+    if (tiles * n_frames > (int64_t(1) << 30)) return fail(ADCT_ERANGE, "too many tiles in one call");
+    a.tiles_per_frame = int32_t(tiles);
+    // 1-D weights: exp(-d^2 / (2 sigma^2)), d = -5..5, normalised (the 2-D window
+    // of unit sum is their outer product)
+    double s = 0.0;
+    for (int d = 0; d < kWin; ++d) s += (a.w[d] = exp(-double((d - 5) * (d - 5)) / (2.0 * 1.5 * 1.5)));
+    for (int d = 0; d < kWin; ++d) a.w[d] /= s;
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const int n = n_frames * n_planes;
+    hipLaunchKernelGGL(k_ssim_zero, dim3((n + 255) / 256), dim3(256), 0, hs, a.acc, n);
+    ADCT_HIP(hipGetLastError());
+    const int64_t waves = tiles * n_frames;
+    hipLaunchKernelGGL(k_ssim, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, hs, a);
+    ADCT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ssim_final, dim3((n + 255) / 256), dim3(256), 0, hs, a.acc, n_frames, n_planes, a);
+    ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
+}

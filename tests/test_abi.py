@@ -180,3 +180,23 @@ def test_batch_empty_and_oversized_sets():
     tids = (ctypes.c_int * 1)(A.T1)
     assert lib.adct_evaluate_batch(FAKE, planes, 0, tids, 1, 1, 63, FAKE, 4, 1, None) == -3
     assert lib.adct_evaluate_batch(FAKE, planes, 1, tids, 0, 1, 63, FAKE, 4, 1, None) == -3
+
+
+def test_ssim_argument_errors_host_only():
+    """adct_ssim validates every argument before it launches anything."""
+    lib = A.lib()
+    FAKE = ctypes.c_void_p(4096)
+    OUT = ctypes.c_void_p(8192)
+    ok = A.planes_struct([(0, 32, 32, 32)])
+    assert lib.adct_ssim(None, 0, FAKE, 0, 1, ok, 1, OUT, None) == -1
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, ok, 1, None, None) == -1
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 0, ok, 1, OUT, None) == -3
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, ok, 0, OUT, None) == -3
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, ok, 5, OUT, None) == -3
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, A.planes_struct([(0, 10, 32, 32)]), 1, OUT, None) == -2
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, A.planes_struct([(0, 32, 10, 32)]), 1, OUT, None) == -2
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, A.planes_struct([(0, 32, 32, 16)]), 1, OUT, None) == -2
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, ok, 1, ctypes.c_void_p(8196), None) == -2
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 2, ok, 1, OUT, None) == -2
+    assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, A.planes_struct([(0, 1 << 14, 1 << 13, 1 << 13)]), 1, OUT,
+                         None) == -3
