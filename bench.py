@@ -144,14 +144,36 @@ def batch_row():
     info = plan.info()
     plan.close()
     evals = len(imgs) * len(names) * 63
+    # mean SSIM over the 45 images against r (Sec. 6.1.1 compares the transforms'
+    # SSIM curves): decode each image with the library, score it with the SSIM kernel
+    rs = [4, 8, 12, 16, 24, 32, 48, 60]
+    tfs = ["DCT", "T1", "LO", "T6"]
+    curve = {t: [] for t in tfs}
+    t0 = time.perf_counter()
+    for r in rs:
+        for t in tfs:
+            vals = []
+            for (o, h, w, _) in planes:
+                img = base[o:o + h * w].view(h, w)
+                rec = torch.empty_like(img)
+                A.evaluate_coding(img, t, r, recon=rec)
+                vals.append(A.ssim(img, rec, None))
+            curve[t].append(round(float(torch.cat(vals).mean().item()), 6))
+    ssim_s = time.perf_counter() - t0
     return {"batch_45img_6tf_r1_63": {
         "ms": round(ms, 3), "evaluations": evals, "evaluations_per_s": round(evals / (ms / 1e3)),
         "Gpixel_evals_per_s": round(off * len(names) * 63 / (ms / 1e3) / 1e9, 1),
         "pixels": off, "schedule": info,
-        "mean_psnr_r10": {n: round(float(psnr[t, 9]), 4) for t, n in enumerate(names)}}}
+        "mean_psnr_r10": {n: round(float(psnr[t, 9]), 4) for t, n in enumerate(names)}},
+        "ssim_vs_r_45img": {"r": rs, **curve,
+                            "T1_above_DCT_at_r": [r for r, a, b in zip(rs, curve["T1"], curve["DCT"]) if a > b],
+                            "seconds": round(ssim_s, 2)}}
 
 
 FILTER_FLOP_PER_PX = 2 * (9 * 32 + 288 * 32 + 288)   # 19,584: forward MACs x 2, per output pixel
+# SSIM per map position: two separable 11-tap passes over 5 maps (x, y, x^2, y^2, xy)
+# as multiply-adds, plus the formula (about 20 operations)
+SSIM_FLOP_PER_MAP_PX = 2 * 2 * 5 * 11 + 20
 
 
 def filter_images(n_train: int, n_val: int):
@@ -218,12 +240,14 @@ def filter_row(data, steps, frames, recon, planes, sse_plain, sse_dct, npix, cod
     torch.cuda.synchronize()
     apply_ms = e0.elapsed_time(e1) / reps
     _, sse_f = A.filter_apply(packed, recon, planes, out=filt, orig=frames)
+    ssim_f = A.ssim(frames, filt, planes).cpu().numpy()
     e0.record()
     keep = A.filter_select(sse_f, sse_dct, recon, planes, filt)
     e1.record()
     torch.cuda.synchronize()
     select_ms = e0.elapsed_time(e1)
     samples = frames.numel()
+    npix_map = [(h - 10) * (w - 10) for _, h, w, _ in planes]
     sf, sp, sd = (x.cpu().numpy().sum(axis=1).astype(np.float64) for x in (sse_f, sse_plain, sse_dct))
     tot = float(sum(npix))
     ps = lambda v: float(np.mean(10 * np.log10(255.0 ** 2 * tot / np.maximum(v, 1))))
@@ -242,6 +266,8 @@ def filter_row(data, steps, frames, recon, planes, sse_plain, sse_dct, npix, cod
                    "psnr_plain": round(ps(sp), 4), "psnr_filtered": round(ps(sf), 4),
                    "psnr_dct": round(ps(sd), 4), "psnr_output": round(ps(final), 4),
                    "gain_vs_plain": round(ps(sf) - ps(sp), 4), "gain_vs_dct": round(ps(sf) - ps(sd), 4),
+                   "ssim_filtered_frame_mean": round(float(np.mean(
+                       (ssim_f * np.array(npix_map)).sum(axis=1) / sum(npix_map))), 6),
                    "frames_kept": int(kept.sum()), "frames": int(len(kept)),
                    "plain_Mpixel_per_s": round(samples / (codec_ms / 1e3) / 1e6, 1),
                    "learned_Mpixel_per_s": round(samples / ((codec_ms + apply_ms + select_ms) / 1e3) / 1e6,
@@ -265,14 +291,15 @@ def main():
                          "-1 = one tile per wave)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the codec shards by frame "
-              f"with no exchange beyond the per-frame SSE, which this build does not launch.",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU "
+              f"path (the codec would shard by frame, exchanging only per-frame squared errors).",
               file=sys.stderr)
         sys.exit(2)
 
     # training images are drawn before the GPU is touched
     fdata = filter_images(args.filter_patches, 4096) if args.filter_patches else None
 
+    import numpy as np
     import torch
 
     import paper_1808_02950_amd as A
@@ -356,6 +383,22 @@ def main():
     # power-of-two step >= 8 the three-term bfloat16 split, else float32 products
     split_form = r <= 16 and step >= 8 and (step & (step - 1)) == 0
 
+    # SSIM of the T1 and exact-DCT reconstructions (float64 GPU kernel), timed apart
+    ssim_t1 = A.ssim(frames, recon, planes)
+    ssim_dct = A.ssim(frames, recon_dct, planes)
+    torch.cuda.synchronize()
+    ev2.record()
+    for _ in range(dct_steps):
+        A.ssim(frames, recon, planes, out=ssim_t1)
+    ev3.record()
+    torch.cuda.synchronize()
+    ssim_ms = ev2.elapsed_time(ev3) / dct_steps
+    map_px = spec.n_frames * sum((h - 10) * (w - 10) for h, w in spec.plane_shapes)
+    ssim_flop = map_px * SSIM_FLOP_PER_MAP_PX
+    st1, sdct = ssim_t1.cpu().numpy(), ssim_dct.cpu().numpy()
+    wts = np.array([(h - 10) * (w - 10) for h, w in spec.plane_shapes], dtype=np.float64)
+    frame_ssim = lambda a: float(np.mean((a * wts).sum(axis=1) / wts.sum()))
+
     out = {
         "metric": "Mpixel/s 8x8 approx-DCT encode+decode at r=10 (% HBM peak); PSNR dB vs exact",
         "value": round(value, 1),
@@ -385,6 +428,11 @@ def main():
                                  "hbm_frac": round(dct_bytes / (dct_ms / 1e3) / 1e9 / peak, 4),
                                  "form": "3-term bf16 split, float32-exact products" if split_form
                                          else "float32 matrix cores"},
+        "ssim": {"T1_frame_mean": round(frame_ssim(st1), 6), "DCT_frame_mean": round(frame_ssim(sdct), 6),
+                 "T1_minus_DCT": round(frame_ssim(st1) - frame_ssim(sdct), 6),
+                 "T1_Y": round(float(st1[:, 0].mean()), 6), "DCT_Y": round(float(sdct[:, 0].mean()), 6),
+                 "kernel_ms": round(ssim_ms, 3), "fp64_tflops": round(ssim_flop / (ssim_ms / 1e3) / 1e12, 1),
+                 "peak_fp64_tflops": 78.6},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
                      "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
