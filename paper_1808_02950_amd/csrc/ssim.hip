@@ -6,8 +6,10 @@
 //
 // One wave computes a tile of the map: 64 output columns (one per lane) x 88
 // output rows.  Input rows stream through it once: each row's two pixels per
-// position go to a per-wave LDS row (x | y << 16), every lane sums its 11
-// horizontal neighbours' x, y, x^2, y^2, xy with the 1-D weights, and that row
+// position (loaded one row ahead) go to a per-wave LDS row (x | y << 16),
+// every lane sums its 11
+// horizontal neighbours' x, y, x^2, y^2, xy with the 1-D weights (mirrored taps
+// added as exact integers first, the weights being symmetric), and that row
 // of horizontal sums is folded into the 11 output rows it reaches with the
 // vertical weights.  Eleven rotating accumulators hold those rows; with the row
 // loop unrolled by 11 every accumulator index is a compile-time constant.  An
@@ -59,29 +61,56 @@ __device__ __forceinline__ double ssim_at(const double (&s)[5]) {
 
 // one input row (relative index i = i0 + U) of the tile; U is the row's
 // position in its group of 11, so every accumulator slot is a constant
+// the four pixel bytes a lane loads for one input row (its column and, for
+// lanes 0..9, the column 64 further), issued one row ahead of their use
+struct RowPix {
+    uint32_t ra, ta, rb, tb;
+};
+
+__device__ __forceinline__ void load_row(const uint8_t *rb, const uint8_t *tb, const SsimPlane &P, int r, int ca,
+                                         int cb, int lane, RowPix &v) {
+    const int64_t base = int64_t(std::min(r, P.H - 1)) * P.pitch;
+    v.ra = rb[base + ca];
+    v.ta = tb[base + ca];
+    if (lane < kWin - 1) {
+        v.rb = rb[base + cb];
+        v.tb = tb[base + cb];
+    }
+}
+
 template <int U>
 __device__ __forceinline__ void ssim_row(const SsimArgs &a, const uint8_t *rb, const uint8_t *tb, const SsimPlane &P,
                                          int r0, int i0, int nout, int ca, int cb, int lane, uint32_t *row,
-                                         double (&acc)[kWin][5], double &sum, bool col_ok) {
+                                         RowPix &nx, double (&acc)[kWin][5], double &sum, bool col_ok) {
     const int i = i0 + U;
     if (i >= nout + kWin - 1) return;                          // wave-uniform
-    const int64_t base = int64_t(std::min(r0 + i, P.H - 1)) * P.pitch;
-    row[lane] = uint32_t(rb[base + ca]) | (uint32_t(tb[base + ca]) << 16);
-    if (lane < kWin - 1) row[64 + lane] = uint32_t(rb[base + cb]) | (uint32_t(tb[base + cb]) << 16);
+    const RowPix cur = nx;
+    if (i + 1 < nout + kWin - 1) load_row(rb, tb, P, r0 + i + 1, ca, cb, lane, nx);
+    row[lane] = cur.ra | (cur.ta << 16);
+    if (lane < kWin - 1) row[64 + lane] = cur.rb | (cur.tb << 16);
     __builtin_amdgcn_wave_barrier();
-    double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int x[kWin], y[kWin];
 #pragma unroll
     for (int b = 0; b < kWin; ++b) {
         const uint32_t v = row[lane + b];
-        const int x = int(v & 0xffffu) - 128, y = int(v >> 16) - 128;
-        const double wb = a.w[b];
-        h[0] = fma(wb, double(x), h[0]);
-        h[1] = fma(wb, double(y), h[1]);
-        h[2] = fma(wb, double(x * x), h[2]);
-        h[3] = fma(wb, double(y * y), h[3]);
-        h[4] = fma(wb, double(x * y), h[4]);
+        x[b] = int(v & 0xffffu) - 128;
+        y[b] = int(v >> 16) - 128;
     }
     __builtin_amdgcn_wave_barrier();
+    // the weights are symmetric: taps b and 10 - b are added as exact integers first
+    const double w5 = a.w[5];
+    double h[5] = {w5 * double(x[5]), w5 * double(y[5]), w5 * double(x[5] * x[5]), w5 * double(y[5] * y[5]),
+                   w5 * double(x[5] * y[5])};
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const int c = kWin - 1 - b;
+        const double wb = a.w[b];
+        h[0] = fma(wb, double(x[b] + x[c]), h[0]);
+        h[1] = fma(wb, double(y[b] + y[c]), h[1]);
+        h[2] = fma(wb, double(x[b] * x[b] + x[c] * x[c]), h[2]);
+        h[3] = fma(wb, double(y[b] * y[b] + y[c] * y[c]), h[3]);
+        h[4] = fma(wb, double(x[b] * y[b] + x[c] * y[c]), h[4]);
+    }
     // this row feeds output rows o = i - d, d = 0..10, of slot (U - d) mod 11
 #pragma unroll
     for (int d = 0; d < kWin; ++d) {
@@ -130,18 +159,20 @@ __global__ __launch_bounds__(256) void k_ssim(const SsimArgs a) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[k][q] = 0.0;
     double sum = 0.0;
+    RowPix nx = {0u, 0u, 0u, 0u};
+    load_row(rb, tb, P, r0, ca, cb, lane, nx);
     for (int i0 = 0; i0 < nout + kWin - 1; i0 += kWin) {
-        ssim_row<0>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<1>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<2>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<3>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<4>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<5>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<6>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<7>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<8>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<9>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
-        ssim_row<10>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, acc, sum, col_ok);
+        ssim_row<0>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<1>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<2>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<3>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<4>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<5>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<6>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<7>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<8>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<9>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
+        ssim_row<10>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
     }
     // fixed point (|map| <= 1, at most 88 entries per lane), then the wave sum
     long long v = llrint(sum * kFix);
