@@ -16,6 +16,7 @@ Modules
   batch     SSE table over images x transforms x retention levels
   postfilter  float64 conv network forward/backward on bfloat16-rounded operands
   ssim      structural similarity of a reconstruction (Gaussian-window local statistics)
+  jam       16- and 32-point matrices by the JAM construction; N x N transform coding
 
 Every function cites the passage of the paper it restates.  Readings taken where
 the paper is silent or ambiguous are stated where they are used.

@@ -2,6 +2,9 @@
 
 TEST INFRASTRUCTURE: see the package docstring.
 
+The same steps serve the 16- and 32-point matrices of the JAM construction
+(Sec. 6.2; see `jam`): the block order is the order of T.
+
 Per 8x8 block A of an 8-bit image:
   forward   B = C_hat A C_hat^T with C_hat = S T           (Sec. 6.1.1, Eq. (1))
             computed as the exact integer stage Y = T A T^T, then B = S Y S
@@ -51,7 +54,7 @@ def zigzag(n: int = N) -> list[tuple[int, int]]:
 def zonal_mask(r: int, n: int = N) -> np.ndarray:
     """Boolean n x n mask of the first r zig-zag coefficients (Sec. 6.1.1)."""
     if not 0 <= r <= n * n:
-        raise ValueError("r must be in [0, 64]")
+        raise ValueError(f"r must be in [0, {n * n}]")
     m = np.zeros((n, n), dtype=bool)
     for i, j in zigzag(n)[:r]:
         m[i, j] = True
@@ -67,17 +70,17 @@ def zz_index_arrays(n: int = N) -> tuple[np.ndarray, np.ndarray]:
 # blocks
 # --------------------------------------------------------------------------
 
-def to_blocks(img: np.ndarray) -> np.ndarray:
-    """(H, W) image -> (H/8 * W/8, 8, 8) blocks in raster order, int64."""
+def to_blocks(img: np.ndarray, n: int = N) -> np.ndarray:
+    """(H, W) image -> (H/n * W/n, n, n) blocks in raster order, int64."""
     h, w = img.shape
-    if h % N or w % N:
-        raise ValueError("H and W must be multiples of 8")
-    b = np.asarray(img, dtype=np.int64).reshape(h // N, N, w // N, N)
-    return b.transpose(0, 2, 1, 3).reshape(-1, N, N)
+    if h % n or w % n:
+        raise ValueError(f"H and W must be multiples of {n}")
+    b = np.asarray(img, dtype=np.int64).reshape(h // n, n, w // n, n)
+    return b.transpose(0, 2, 1, 3).reshape(-1, n, n)
 
 
-def from_blocks(blocks: np.ndarray, h: int, w: int) -> np.ndarray:
-    b = np.asarray(blocks).reshape(h // N, w // N, N, N).transpose(0, 2, 1, 3)
+def from_blocks(blocks: np.ndarray, h: int, w: int, n: int = N) -> np.ndarray:
+    b = np.asarray(blocks).reshape(h // n, w // n, n, n).transpose(0, 2, 1, 3)
     return b.reshape(h, w)
 
 
@@ -105,15 +108,15 @@ def forward_real(blocks: np.ndarray, c: np.ndarray) -> np.ndarray:
 
 
 def take_zigzag(coef: np.ndarray, r: int) -> np.ndarray:
-    """(nb, 8, 8) -> (nb, r) in zig-zag order."""
-    zi, zj = zz_index_arrays()
+    """(nb, n, n) -> (nb, r) in zig-zag order."""
+    zi, zj = zz_index_arrays(coef.shape[-1])
     return coef[:, zi[:r], zj[:r]]
 
 
-def put_zigzag(vals: np.ndarray, r: int, dtype) -> np.ndarray:
-    """(nb, r) zig-zag prefix -> (nb, 8, 8) with the discarded entries 0."""
-    zi, zj = zz_index_arrays()
-    out = np.zeros((vals.shape[0], N, N), dtype=dtype)
+def put_zigzag(vals: np.ndarray, r: int, dtype, n: int = N) -> np.ndarray:
+    """(nb, r) zig-zag prefix -> (nb, n, n) with the discarded entries 0."""
+    zi, zj = zz_index_arrays(n)
+    out = np.zeros((vals.shape[0], n, n), dtype=dtype)
     out[:, zi[:r], zj[:r]] = vals
     return out
 
@@ -134,7 +137,7 @@ def quantize(y_zz: np.ndarray, t: np.ndarray, r: int, step: int) -> np.ndarray:
     it is rounded in exact integer arithmetic; otherwise it is irrational
     (never an exact half) and float64 decides."""
     n = row_norms2(t)
-    zi, zj = zz_index_arrays()
+    zi, zj = zz_index_arrays(np.asarray(t).shape[0])
     y_zz = np.asarray(y_zz, dtype=np.int64)
     q = np.empty_like(y_zz)
     s = scale_diag(t)
@@ -207,7 +210,7 @@ def _settle_near_halves(rounded, real, q_zz, t, r, step, window=1e-6):
         return
     t = np.asarray(t, dtype=np.int64)
     n = row_norms2(t)
-    zz = zigzag()[:r]
+    zz = zigzag(t.shape[0])[:r]
     with localcontext() as ctx:
         ctx.prec = 60
         inv_sqrt = {(k, l): 1 / Decimal(int(n[k] * n[l])).sqrt() for k, l in zz}
@@ -257,10 +260,12 @@ def encode(img: np.ndarray, t: np.ndarray, r: int, step: int = 0) -> dict:
     """Forward transform of every block; first r zig-zag coefficients.
 
     Returns coef_int (nb, r): the exact integer stage Y (or, with step > 0, the
-    quantised q), and coef_scaled (nb, r): B = s_k s_l Y in float64."""
-    if not 1 <= r <= 64:
-        raise ValueError("r must be in [1, 64]")
-    blocks = to_blocks(img)
+    quantised q), and coef_scaled (nb, r): B = s_k s_l Y in float64.  The block
+    size n is the order of T (8, or 16 and 32 for the JAM matrices)."""
+    n = np.asarray(t).shape[0]
+    if not 1 <= r <= n * n:
+        raise ValueError(f"r must be in [1, {n * n}]")
+    blocks = to_blocks(img, n)
     y = forward_int(blocks, t)
     y_zz = take_zigzag(y, r)
     b_zz = take_zigzag(scale_coeffs(y, t), r)
@@ -273,18 +278,19 @@ def decode(coef_int: np.ndarray, t: np.ndarray, r: int, h: int, w: int,
            step: int = 0) -> dict:
     """Inverse of `encode`'s integer output.  Returns the rounded, clipped uint8
     image `rec` and the real-valued reconstruction `real` (float64)."""
+    n = np.asarray(t).shape[0]
     if step == 0:
-        y_full = put_zigzag(coef_int, r, np.int64)
+        y_full = put_zigzag(coef_int, r, np.int64, n)
         num, big_l = inverse_exact(y_full, t)
         rounded = rne_div(num, big_l)
         real = num.astype(np.float64) / big_l
     else:
-        bq = put_zigzag(np.asarray(coef_int, dtype=np.float64) * step, r, np.float64)
+        bq = put_zigzag(np.asarray(coef_int, dtype=np.float64) * step, r, np.float64, n)
         real = inverse_real(bq, approx_matrix(t))
         rounded = np.rint(real)
         _settle_near_halves(rounded, real, np.asarray(coef_int, dtype=np.int64), t, r, step)
-    return {"rec": from_blocks(clip_u8(rounded), h, w),
-            "real": from_blocks(real, h, w)}
+    return {"rec": from_blocks(clip_u8(rounded), h, w, n),
+            "real": from_blocks(real, h, w, n)}
 
 
 def evaluate(img: np.ndarray, t: np.ndarray, r: int, step: int = 0) -> dict:
