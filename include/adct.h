@@ -195,6 +195,44 @@ adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, in
                                  int16_t *coef, uint8_t *recon, int64_t frame_stride_out,
                                  uint64_t *sse, adct_stream_t stream);
 
+/* ---------------------------------------------------------------- 16 / 32 points */
+
+/* The N-point matrix (N = 16 or 32) that the Jridi-Alfalou-Meher construction
+ * grows from an 8-point one (Sec. 6.2): row 2i = [t_i, rev(t_i)], row 2i + 1 =
+ * [t_i, -rev(t_i)] with t_i row i of the N/2-point matrix (the sign convention
+ * of the 16- and 32-point matrices the paper prints; the recursion as written
+ * negates some odd rows, which changes no reconstruction).  Only base = ADCT_T1.
+ * T: host int8 [N * N] row-major; n: host int32 [N], n[k] = (T T^T)_kk.  Host
+ * only.  Errors: ADCT_EINVAL null; ADCT_ENOTSUP other base; ADCT_ERANGE N. */
+adct_status adct_jam_matrix(adct_transform_id base, int N, int8_t *T, int32_t *n);
+
+/* Transform coding with N x N blocks and the matrix of adct_jam_matrix (Sec. 6.2
+ * for the matrices, Sec. 6.1.1 for the coder): per block B = C_hat A C_hat^T,
+ * C_hat = S T, keep the first r coefficients of the N x N JPEG zig-zag scan,
+ * optionally quantise (q = round-half-away(B / quant_step)), reconstruct
+ * C_hat^T B' C_hat, round half to even, clip to [0, 255] and accumulate the
+ * squared error.  Planes of any size: a plane whose sides are not multiples of
+ * N is extended by repeating its last row and column, and only its own pixels
+ * are written and scored.  frames / planes / recon / frame strides as in
+ * adct_evaluate_stream (device memory; recon uses the input's offsets and
+ * pitches).  coef (nullable): device int32, 4-byte aligned, [block][r] with
+ * the planes' blocks numbered consecutively per frame in plane order, raster
+ * order inside a plane; values are the exact integer stage Y (quant_step = 0)
+ * or the levels q.  sse: device uint64 [n_frames][n_planes], 8-byte aligned,
+ * zeroed by the call then accumulated.  quant_step = 0 reconstructs in exact
+ * rational arithmetic; otherwise float64, and quant_step must be a multiple of
+ * N (then no reconstruction can sit exactly on a half).
+ * Errors: ADCT_EINVAL null frames / planes / sse; ADCT_ENOTSUP base other than
+ * ADCT_T1, quant_step not a multiple of N; ADCT_ERANGE N not 16 or 32, r not in
+ * [1, N * N], quant_step not in [0, 4096], n_frames < 1, n_planes not in [1, 4],
+ * too many blocks; ADCT_EDIM H or W < 1, pitch < W, negative offset, unaligned
+ * sse or coef, non-positive frame stride with several frames. */
+adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                     const adct_plane *planes, int n_planes,
+                                     adct_transform_id base, int N, int r, int quant_step,
+                                     int32_t *coef, uint8_t *recon, int64_t frame_stride_out,
+                                     uint64_t *sse, adct_stream_t stream);
+
 /* ---------------------------------------------------------------- search */
 
 /* Search modes of adct_derive_transform (Sec. 3.5 and 4.1).  Exact ties in

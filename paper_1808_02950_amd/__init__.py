@@ -65,6 +65,9 @@ _SIGNATURES = {
     "adct_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I,
                                   ctypes.POINTER(Matrix), _I, _I, _P, _P, _I64, _P, _P]),
     "adct_ssim": (_I, [_P, _I64, _P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _P]),
+    "adct_jam_matrix": (_I, [_I, _I, _P, _P]),
+    "adct_jam_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I, _I, _I, _I,
+                                      _P, _P, _I64, _P, _P]),
     "adct_derive_transform": (_I, [_P, _I, _I, _P, _I, _I, ctypes.POINTER(Matrix), _I,
                                    ctypes.POINTER(_I), _P, ctypes.POINTER(_I64),
                                    ctypes.POINTER(_I64), _P]),
@@ -276,6 +279,55 @@ def ssim(ref, test, planes, out=None, stream=None):
     _check(lib().adct_ssim(_ptr(ref), fs_r, _ptr(test), fs_t, nf, arr, len(planes), _ptr(out),
                            _stream(stream)))
     return out
+
+
+def jam_matrix(n: int, base="T1"):
+    """adct_jam_matrix: the n-point matrix (n = 16 or 32) as numpy int8 (n, n)
+    and its row norms as int32 (n,)."""
+    import numpy as np
+    t = np.zeros((n, n), dtype=np.int8)
+    nr = np.zeros(n, dtype=np.int32)
+    _check(lib().adct_jam_matrix(_tid(base), n, t.ctypes.data, nr.ctypes.data))
+    return t, nr
+
+
+def jam_blocks_per_frame(planes, n: int) -> int:
+    return sum(((h + n - 1) // n) * ((w + n - 1) // n) for _, h, w, _ in planes)
+
+
+def jam_evaluate_stream(frames, planes, n: int, r: int, quant_step: int = 0, coef=None, recon=None,
+                        sse=None, base="T1", stream=None):
+    """adct_jam_evaluate_stream over frames (uint8 CUDA tensor (n_frames, frame_bytes)),
+    n x n blocks.  planes: list of (offset, H, W, pitch).  Returns the device SSE
+    tensor (n_frames, n_planes) int64 (uint64 values); does not synchronise."""
+    import torch
+    _need_cuda(frames, torch.uint8, "frames")
+    nf = frames.shape[0]
+    # every byte the kernel touches must lie inside the tensors
+    for name, buf in (("frames", frames), ("recon", recon)):
+        if buf is None:
+            continue
+        if buf.dim() != 2 or buf.stride(1) != 1 or buf.shape[0] != nf:
+            raise ValueError(f"{name} must be (n_frames, frame_bytes) with unit inner stride")
+        for off, h, w, pitch in planes:
+            if h >= 1 and w >= 1 and off + (h - 1) * pitch + w > buf.shape[1]:
+                raise ValueError(f"a plane reaches past the end of a frame of {name}")
+    if sse is None:
+        sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
+    elif sse.numel() < nf * len(planes):
+        raise ValueError("sse is too small")
+    if coef is not None:
+        _need_cuda(coef, torch.int32, "coef")
+        if not coef.is_contiguous() or coef.numel() < nf * jam_blocks_per_frame(planes, n) * r:
+            raise ValueError("coef must be contiguous with n_frames * blocks * r entries")
+    if recon is not None:
+        _need_cuda(recon, torch.uint8, "recon")
+    arr = planes_struct(planes)
+    _check(lib().adct_jam_evaluate_stream(_ptr(frames), frames.stride(0), nf, arr, len(planes), _tid(base),
+                                          n, r, quant_step, _ptr(coef), _ptr(recon),
+                                          recon.stride(0) if recon is not None else 0,
+                                          _ptr(sse), _stream(stream)))
+    return sse
 
 
 def stream_blocks_per_frame(planes) -> int:

@@ -200,3 +200,49 @@ def test_ssim_argument_errors_host_only():
     assert lib.adct_ssim(FAKE, 0, FAKE, 0, 2, ok, 1, OUT, None) == -2
     assert lib.adct_ssim(FAKE, 0, FAKE, 0, 1, A.planes_struct([(0, 1 << 14, 1 << 13, 1 << 13)]), 1, OUT,
                          None) == -3
+
+
+def test_jam_matrix_host_only():
+    """adct_jam_matrix (host only) returns the oracle's 16- and 32-point matrices."""
+    from oracle import jam
+    from oracle import matrices as M
+    for n in (16, 32):
+        t, nr = A.jam_matrix(n)
+        want = jam.jam_n(M.T1, n)
+        assert np.array_equal(t.astype(np.int64), want)
+        assert np.array_equal(nr.astype(np.int64), np.sum(want * want, axis=1))
+    lib = A.lib()
+    buf = (ctypes.c_int8 * 1024)()
+    nb = (ctypes.c_int32 * 32)()
+    assert lib.adct_jam_matrix(A.TRANSFORM_IDS["T1"], 8, buf, nb) == -3
+    assert lib.adct_jam_matrix(A.TRANSFORM_IDS["LO"], 16, buf, nb) == -7
+    assert lib.adct_jam_matrix(A.TRANSFORM_IDS["T1"], 16, None, nb) == -1
+
+
+def test_jam_argument_errors_host_only():
+    """adct_jam_evaluate_stream validates every argument before it launches anything."""
+    lib = A.lib()
+    FAKE = ctypes.c_void_p(4096)
+    SSE = ctypes.c_void_p(8192)
+    T1 = A.TRANSFORM_IDS["T1"]
+    ok = A.planes_struct([(0, 40, 40, 40)])
+
+    def call(frames=FAKE, fs=0, nf=1, planes=ok, npl=1, base=T1, n=16, r=10, step=16, coef=None,
+             sse=SSE):
+        return lib.adct_jam_evaluate_stream(frames, fs, nf, planes, npl, base, n, r, step, coef, None,
+                                            0, sse, None)
+    assert call(frames=None) == -1
+    assert call(sse=None) == -1
+    assert call(base=A.TRANSFORM_IDS["T6"]) == -7
+    assert call(n=8) == -3 and call(n=64) == -3
+    assert call(r=0) == -3 and call(r=257) == -3 and call(n=32, r=1025) == -3
+    assert call(step=-16) == -3 and call(step=4112) == -3
+    assert call(step=8) == -7 and call(n=32, step=16) == -7
+    assert call(nf=0) == -3
+    assert call(npl=0) == -3 and call(npl=5) == -3
+    assert call(nf=2, fs=0) == -2
+    assert call(planes=A.planes_struct([(0, 0, 40, 40)])) == -2
+    assert call(planes=A.planes_struct([(0, 40, 40, 39)])) == -2
+    assert call(planes=A.planes_struct([(-1, 40, 40, 40)])) == -2
+    assert call(sse=ctypes.c_void_p(8196)) == -2
+    assert call(coef=ctypes.c_void_p(4098)) == -2
