@@ -399,6 +399,34 @@ def main():
     wts = np.array([(h - 10) * (w - 10) for h, w in spec.plane_shapes], dtype=np.float64)
     frame_ssim = lambda a: float(np.mean((a * wts).sum(axis=1) / wts.sum()))
 
+    # 16- and 32-point JAM matrices (Sec. 6.2) on the same stream, with the
+    # coefficient budget per pixel of r = 10 of 64 (40 of 256, 160 of 1024); the
+    # 32-point coder needs a step that is a multiple of 32, so the 8-point T1
+    # is also scored at step 32 beside it
+    jam = {}
+    recon_j = torch.empty_like(frames)
+    sse_j = torch.empty_like(sse)
+    for n_j, r_j, s_j in ((16, 40, 16), (32, 160, 32)):
+        A.jam_evaluate_stream(frames, planes, n_j, r_j, s_j, recon=recon_j, sse=sse_j)
+        torch.cuda.synchronize()
+        ev2.record()
+        for _ in range(dct_steps):
+            A.jam_evaluate_stream(frames, planes, n_j, r_j, s_j, recon=recon_j, sse=sse_j)
+        ev3.record()
+        torch.cuda.synchronize()
+        ms_j = ev2.elapsed_time(ev3) / dct_steps
+        pj, _ = psnrs(sse_j)
+        sj = A.ssim(frames, recon_j, planes).cpu().numpy()
+        jam[f"T1_{n_j}x{n_j}_r{r_j}_q{s_j}"] = {
+            "kernel_ms": round(ms_j, 4),
+            "Mpixel_per_s": round(samples / (ms_j / 1e3) / 1e6, 1),
+            "GB_per_s": round(2 * samples / (ms_j / 1e3) / 1e9, 1),
+            "hbm_frac": round(2 * samples / (ms_j / 1e3) / 1e9 / peak, 4),
+            "psnr_frame_mean": round(pj, 4), "ssim_frame_mean": round(frame_ssim(sj), 6)}
+    A.evaluate_stream(frames, planes, "T1", r, 32, sse=sse_j)
+    jam["T1_8x8_r10_q32_psnr_frame_mean"] = round(psnrs(sse_j)[0], 4)
+    jam["T1_8x8_r10_q16_psnr_frame_mean"] = round(psnr_frame, 4)
+
     out = {
         "metric": "Mpixel/s 8x8 approx-DCT encode+decode at r=10 (% HBM peak); PSNR dB vs exact",
         "value": round(value, 1),
@@ -433,6 +461,7 @@ def main():
                  "T1_Y": round(float(st1[:, 0].mean()), 6), "DCT_Y": round(float(sdct[:, 0].mean()), 6),
                  "kernel_ms": round(ssim_ms, 3), "fp64_tflops": round(ssim_flop / (ssim_ms / 1e3) / 1e12, 1),
                  "peak_fp64_tflops": 78.6},
+        "jam_16_32_point": jam,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
                      "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},

@@ -152,7 +152,7 @@ struct JamArgs {
     int64_t fs_in, fs_out;
     int32_t n_frames, n_planes;
     int32_t tiles_per_frame, blocks_per_frame;
-    int32_t r, band, P;   // prefix length, its last diagonal, LDS row length
+    int32_t r, band;      // prefix length, the last anti-diagonal it reaches (at most N - 1)
     int32_t step;
     double inv_step;
     double step_d;
@@ -191,8 +191,8 @@ __device__ __forceinline__ int rne_div_exact(double n, double L, double inv_L) {
     if (rem < 0.0) { q -= 1.0; rem += L; }
     if (rem >= L) { q += 1.0; rem -= L; }
     const double twice = rem + rem;
-    if (twice > L || (twice == L && fmod(q, 2.0) != 0.0)) q += 1.0;
-    return int(q);
+    const int qi = int(q);
+    return qi + ((twice > L || (twice == L && (qi & 1))) ? 1 : 0);
 }
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
@@ -221,10 +221,199 @@ __device__ __forceinline__ JTile jtile_of(const JamArgs &a, int g) {
 
 // ------------------------------------------------------------------ kernel
 
-template <int N, bool QUANT>
+// Where one lane's row of one tile lives.
+template <int N>
+struct JRow {
+    int f, p, by, bx, x0, y;
+    bool active, full;
+};
+
+template <int N>
+__device__ __forceinline__ JRow<N> jrow_of(const JamArgs &a, int g, int b, int j) {
+    constexpr int WB = 64 / N;
+    const JTile t = jtile_of(a, g);
+    const JamPlane &Pl = a.pl[t.p];
+    JRow<N> r;
+    r.f = t.f;
+    r.p = t.p;
+    r.by = t.by;
+    r.bx = t.tx * WB + b;
+    r.active = r.bx < Pl.nbx;
+    r.x0 = (r.active ? r.bx : Pl.nbx - 1) * N;   // idle lanes read the last block
+    r.y = t.by * N + j;
+    r.full = r.x0 + N <= Pl.W;
+    return r;
+}
+
+// The lane's N pixels (rows and columns past the plane repeat its last ones).
+template <int N>
+__device__ __forceinline__ void load_row(const JamArgs &a, const JRow<N> &r, uint32_t (&pix)[N / 4]) {
+    const JamPlane &Pl = a.pl[r.p];
+    const uint8_t *src = a.in + int64_t(r.f) * a.fs_in + Pl.in_off +
+                         int64_t(min(r.y, Pl.H - 1)) * Pl.pitch_in;
+    if (r.full) {
+#pragma unroll
+        for (int v = 0; v < N / 16; ++v) {
+            const u32x4 w = __builtin_nontemporal_load((const u32x4 *)(src + r.x0 + 16 * v));
+            pix[4 * v] = w.x;
+            pix[4 * v + 1] = w.y;
+            pix[4 * v + 2] = w.z;
+            pix[4 * v + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < N / 4; ++v) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) w |= uint32_t(src[min(r.x0 + 4 * v + m, Pl.W - 1)]) << (8 * m);
+            pix[v] = w;
+        }
+    }
+}
+
+// Per-lane constants of the lane's column l (row-norm class of l fixed).
+struct ColConst {
+    double sk[3];     // s_k s_l / step by class of k (quantiser estimate)
+    double dq[3];     // step s_k s_l (dequantisation)
+    int dd[3];        // step mu where n_k n_l = mu^2, else -1 (no exact ties)
+    int cex[3];       // L1 / n_k (exact inverse)
+    int cexl;         // L1 / n_l
+    uint32_t keep;    // bit k: coefficient (k, l) is inside the zig-zag prefix
+};
+
+template <int N, int BAND, bool QUANT>
+__device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw, const uint32_t (&pix)[N / 4],
+                                             const ColConst &cc, int32_t *zs, double *us, int lane, int b,
+                                             int j, unsigned long long &acc, int &acc_fp) {
+    constexpr int NW = N / 4;
+    constexpr int P = (BAND + 1) | 1;     // odd LDS row length: conflict-free columns
+    const JamPlane &Pl = a.pl[rw.p];
+
+    // ---- row transform; the columns 0..band go to LDS
+    {
+        int xin[N], z[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) xin[m] = int((pix[m >> 2] >> (8 * (m & 3))) & 0xffu);
+        jam_fwd<N>(xin, z);
+        __syncthreads();                  // the previous tile's readers are done
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+            if (l <= BAND) zs[lane * P + l] = z[l];
+    }
+    __syncthreads();
+
+    // ---- column transform, zonal prefix, quantiser, column inverse
+    {
+        const int l = j;
+        const int lc = min(l, P - 1);
+        int col[N], Y[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) col[x] = zs[(b * N + x) * P + lc];
+        jam_fwd<N>(col, Y);
+        double B[N], U[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            B[k] = 0.0;
+            if (k > BAND) continue;       // no column keeps row k
+            const int ck = norm_class<N>(k);
+            const bool keep = (cc.keep >> k) & 1u;
+            int q = Y[k];
+            if constexpr (QUANT) {
+                // round-half-away(Y s_k s_l / step): the nearest integer m in float64
+                // is right unless the quotient is an exact half (possible only where
+                // n_k n_l = mu^2, dd = step mu; elsewhere dd = -1 and no test can
+                // hold); at a half m may have gone either way, and moves away from
+                // zero if it went towards it: m + 1/2 = Y / dd for Y > 0, m - 1/2 =
+                // Y / dd for Y < 0
+                int m = __double2loint(fma(double(q), cc.sk[ck], 6755399441055744.0));
+                const int t1 = (2 * m + 1) * cc.dd[ck];
+                const int t2 = t1 - 2 * cc.dd[ck];
+                m += (q > 0 && 2 * q == t1) ? 1 : 0;
+                m -= (q < 0 && 2 * q == t2) ? 1 : 0;
+                q = keep ? m : 0;
+                B[k] = double(q) * cc.dq[ck];
+            } else {
+                q = keep ? q : 0;
+                B[k] = double(q * cc.cex[ck]) * double(cc.cexl);
+            }
+            if (a.coef && keep && rw.active) {
+                const int64_t gblk = int64_t(rw.f) * a.blocks_per_frame + Pl.block_off +
+                                     int64_t(rw.by) * Pl.nbx + rw.bx;
+                a.coef[gblk * a.r + zz_pos<N>(k, l)] = q;
+            }
+        }
+        jam_inv<N>(B, U);
+        if (j < P) {
+#pragma unroll
+            for (int x = 0; x < N; ++x) us[(b * N + x) * P + j] = U[x];
+        }
+    }
+    __syncthreads();
+
+    // ---- row inverse, rounding, store, squared error
+    double V[N], A[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) V[l] = (l <= BAND) ? us[lane * P + l] : 0.0;
+    jam_inv<N>(V, A);
+    uint32_t o[NW];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) o[v] = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        int px;
+        if constexpr (QUANT) px = min(max(__double2loint(A[m] + 6755399441055744.0), 0), 255);
+        else px = rne_div_exact(A[m], a.L, a.inv_L);
+        o[m >> 2] |= uint32_t(px) << (8 * (m & 3));
+    }
+    unsigned e = 0;
+    if (rw.active && rw.y < Pl.H) {
+        // squared error from byte dot products, bytes past the plane masked off:
+        // sum (q - a)^2 = sum q^2 + sum a^2 - 2 sum q a
+        const int ncol = min(N, Pl.W - rw.x0);
+        unsigned sq = 0, cross = 0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            const int nb = min(max(ncol - 4 * v, 0), 4);
+            const uint32_t msk = nb >= 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1u);
+            const uint32_t ov = o[v] & msk, pv = pix[v] & msk;
+            sq = __builtin_amdgcn_udot4(ov, ov, sq, false);
+            sq = __builtin_amdgcn_udot4(pv, pv, sq, false);
+            cross = __builtin_amdgcn_udot4(ov, pv, cross, false);
+        }
+        e = sq - 2u * cross;
+        if (a.out) {
+            uint8_t *dst = a.out + int64_t(rw.f) * a.fs_out + Pl.out_off + int64_t(rw.y) * Pl.pitch_out + rw.x0;
+            if (rw.full) {
+#pragma unroll
+                for (int v = 0; v < NW / 4; ++v) {
+                    u32x4 w;
+                    w.x = o[4 * v];
+                    w.y = o[4 * v + 1];
+                    w.z = o[4 * v + 2];
+                    w.w = o[4 * v + 3];
+                    __builtin_nontemporal_store(w, (u32x4 *)(dst + 16 * v));
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < N; ++m)
+                    if (m < ncol) dst[m] = uint8_t(o[m >> 2] >> (8 * (m & 3)));
+            }
+        }
+    }
+    // squared errors: one atomic per (frame, plane) run of the wave
+    const int fp = rw.f * a.n_planes + rw.p;
+    if (fp != acc_fp) {
+        if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
+        acc = 0;
+        acc_fp = fp;
+    }
+    acc += wave_sum(e);
+}
+
+template <int N, int BAND, bool QUANT>
 __global__ __launch_bounds__(64) void k_jam(const JamArgs a) {
-    constexpr int WB = 64 / N;          // blocks per tile
-    constexpr int NW = N / 4;           // pixel words per row
+    constexpr int NW = N / 4;
+    constexpr int P = (BAND + 1) | 1;
     // two LDS areas, so that the column pass can store its inverse while other
     // lanes may still be reading their columns: rows of the forward pass (int32)
     // and columns of the inverse (double), both 64 x P
@@ -232,166 +421,53 @@ __global__ __launch_bounds__(64) void k_jam(const JamArgs a) {
     const int lane = threadIdx.x;
     const int b = lane / N, j = lane - b * N;     // block in tile, row (then column)
     const int total = a.n_frames * a.tiles_per_frame;
-    const int P = a.P;
-    const int band = a.band;
     int32_t *zs = reinterpret_cast<int32_t *>(lds_raw);
     double *us = lds_raw + 32 * P;
 
-    // per-lane quantiser constants for column class cl = class of l = j
-    const int cl = norm_class<N>(j);
-    double skl_l[3];
-    int mu_l[3];
-    float i2_l[3];
+    // constants of the lane's column l = j
+    ColConst cc;
+    {
+        const int cl = norm_class<N>(j);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        skl_l[c] = cl == 0 ? a.skl[c][0] : cl == 1 ? a.skl[c][1] : a.skl[c][2];
-        mu_l[c] = cl == 0 ? a.mu[c][0] : cl == 1 ? a.mu[c][1] : a.mu[c][2];
-        i2_l[c] = cl == 0 ? a.inv2mu[c][0] : cl == 1 ? a.inv2mu[c][1] : a.inv2mu[c][2];
+        for (int c = 0; c < 3; ++c) {
+            const double skl = cl == 0 ? a.skl[c][0] : cl == 1 ? a.skl[c][1] : a.skl[c][2];
+            const int mu = cl == 0 ? a.mu[c][0] : cl == 1 ? a.mu[c][1] : a.mu[c][2];
+            cc.sk[c] = skl * a.inv_step;
+            cc.dq[c] = skl * a.step_d;
+            cc.dd[c] = mu ? mu * a.step : -1;
+            cc.cex[c] = a.cexact[c];
+        }
+        cc.cexl = cl == 0 ? a.cexact[0] : cl == 1 ? a.cexact[1] : a.cexact[2];
+        cc.keep = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) cc.keep |= (zz_pos<N>(k, j) < a.r) ? (1u << k) : 0u;
     }
-    const int cexl = cl == 0 ? a.cexact[0] : cl == 1 ? a.cexact[1] : a.cexact[2];
 
     unsigned long long acc = 0;
     int acc_fp = -1;
-
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const JTile t = jtile_of(a, g);
-        const JamPlane &Pl = a.pl[t.p];
-        const int bx = t.tx * WB + b;
-        const bool active = bx < Pl.nbx;
-        const int bxc = active ? bx : Pl.nbx - 1;
-        const int x0 = bxc * N;
-        const int y = t.by * N + j;
-        const int ys = min(y, Pl.H - 1);
-        const bool full = x0 + N <= Pl.W;
-
-        // ---- load the lane's row (edge rows and columns repeat the last one)
-        const uint8_t *src = a.in + int64_t(t.f) * a.fs_in + Pl.in_off + int64_t(ys) * Pl.pitch_in;
-        uint32_t pix[NW];
-        if (full) {
-#pragma unroll
-            for (int v = 0; v < NW / 4; ++v) {
-                const u32x4 w = __builtin_nontemporal_load((const u32x4 *)(src + x0 + 16 * v));
-                pix[4 * v] = w.x;
-                pix[4 * v + 1] = w.y;
-                pix[4 * v + 2] = w.z;
-                pix[4 * v + 3] = w.w;
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < NW; ++v) {
-                uint32_t w = 0;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) w |= uint32_t(src[min(x0 + 4 * v + m, Pl.W - 1)]) << (8 * m);
-                pix[v] = w;
-            }
-        }
-
-        // ---- row transform; the columns 0..band go to LDS
-        {
-            int xin[N], z[N];
-#pragma unroll
-            for (int m = 0; m < N; ++m) xin[m] = int((pix[m >> 2] >> (8 * (m & 3))) & 0xffu);
-            jam_fwd<N>(xin, z);
-            __syncthreads();              // the previous tile's readers are done
-#pragma unroll
-            for (int l = 0; l < N; ++l)
-                if (l <= band) zs[lane * P + l] = z[l];
-        }
-        __syncthreads();
-
-        // ---- column transform, zonal prefix, quantiser, column inverse
-        double U[N];
-        {
-            const int l = j;
-            const int lc = min(l, P - 1);
-            int col[N], Y[N];
-#pragma unroll
-            for (int x = 0; x < N; ++x) col[x] = zs[(b * N + x) * P + lc];
-            jam_fwd<N>(col, Y);
-            const int64_t gblk = int64_t(t.f) * a.blocks_per_frame + Pl.block_off +
-                                 int64_t(t.by) * Pl.nbx + bx;
-            double B[N];
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const int ck = norm_class<N>(k);
-                const int z = zz_pos<N>(k, l);
-                const bool keep = z < a.r;
-                int q = Y[k];
-                double bk;
-                if constexpr (QUANT) {
-                    const int mu = mu_l[ck];
-                    q = mu ? quant_rational(q, a.step * mu, i2_l[ck] * float(1.0 / a.step))
-                           : (q < 0 ? -rne_i32(double(-q) * skl_l[ck] * a.inv_step)
-                                    : rne_i32(double(q) * skl_l[ck] * a.inv_step));
-                    bk = double(q) * a.step_d * skl_l[ck];
-                } else {
-                    bk = double(q * a.cexact[ck]) * double(cexl);
-                }
-                if (keep && active && a.coef) a.coef[gblk * a.r + z] = q;
-                B[k] = keep ? bk : 0.0;
-            }
-            jam_inv<N>(B, U);
-        }
-        if (j < P) {
-#pragma unroll
-            for (int x = 0; x < N; ++x) us[(b * N + x) * P + j] = U[x];
-        }
-        __syncthreads();
-
-        // ---- row inverse, rounding, store, squared error
-        {
-            double V[N], A[N];
-#pragma unroll
-            for (int l = 0; l < N; ++l) V[l] = (l <= band) ? us[lane * P + l] : 0.0;
-            jam_inv<N>(V, A);
-            uint32_t o[NW];
-#pragma unroll
-            for (int v = 0; v < NW; ++v) o[v] = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                int px;
-                if constexpr (QUANT) px = min(max(rne_i32(A[m]), 0), 255);
-                else px = rne_div_exact(A[m], a.L, a.inv_L);
-                o[m >> 2] |= uint32_t(px) << (8 * (m & 3));
-            }
-            const bool row_ok = active && y < Pl.H;
-            unsigned e = 0;
-            if (row_ok) {
-                const int ncol = min(N, Pl.W - x0);
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const int d = int((o[m >> 2] >> (8 * (m & 3))) & 0xffu) -
-                                  int((pix[m >> 2] >> (8 * (m & 3))) & 0xffu);
-                    e += (m < ncol) ? unsigned(d * d) : 0u;
-                }
-                if (a.out) {
-                    uint8_t *dst = a.out + int64_t(t.f) * a.fs_out + Pl.out_off + int64_t(y) * Pl.pitch_out + x0;
-                    if (full) {
-#pragma unroll
-                        for (int v = 0; v < NW / 4; ++v) {
-                            u32x4 w;
-                            w.x = o[4 * v];
-                            w.y = o[4 * v + 1];
-                            w.z = o[4 * v + 2];
-                            w.w = o[4 * v + 3];
-                            __builtin_nontemporal_store(w, (u32x4 *)(dst + 16 * v));
-                        }
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < N; ++m)
-                            if (m < ncol) dst[m] = uint8_t(o[m >> 2] >> (8 * (m & 3)));
-                    }
-                }
-            }
-            // squared errors: one atomic per (frame, plane) run of the wave
-            const int fp = t.f * a.n_planes + t.p;
-            if (fp != acc_fp) {
-                if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
-                acc = 0;
-                acc_fp = fp;
-            }
-            acc += wave_sum(e);
-        }
+    int g = blockIdx.x;
+    if (g >= total) return;
+    // the next tile's row loads are issued before the current tile is processed,
+    // on every pass (the last pass re-reads its own tile), so no branch joins
+    // paths with loads in flight
+    uint32_t pa[NW], pb[NW];
+    JRow<N> ra = jrow_of<N>(a, g, b, j), rb = ra;
+    load_row<N>(a, ra, pa);
+    while (true) {
+        int nx = g + int(gridDim.x);
+        bool more = nx < total;
+        rb = jrow_of<N>(a, more ? nx : g, b, j);
+        load_row<N>(a, rb, pb);
+        process_tile<N, BAND, QUANT>(a, ra, pa, cc, zs, us, lane, b, j, acc, acc_fp);
+        if (!more) break;
+        g = nx;
+        nx = g + int(gridDim.x);
+        more = nx < total;
+        ra = jrow_of<N>(a, more ? nx : g, b, j);
+        load_row<N>(a, ra, pa);
+        process_tile<N, BAND, QUANT>(a, rb, pb, cc, zs, us, lane, b, j, acc, acc_fp);
+        if (!more) break;
+        g = nx;
     }
     if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
 }
@@ -401,10 +477,11 @@ __global__ void k_jam_zero(unsigned long long *p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
-template <int N, bool QUANT>
+template <int N, int BAND, bool QUANT>
 adct_status launch(const JamArgs &a, hipStream_t s) {
-    auto kern = k_jam<N, QUANT>;
-    const size_t lds = size_t(64) * a.P * (sizeof(int32_t) + sizeof(double));
+    auto kern = k_jam<N, BAND, QUANT>;
+    constexpr int P = (BAND + 1) | 1;
+    const size_t lds = size_t(64) * P * (sizeof(int32_t) + sizeof(double));
     int dev = 0, cus = 0, per_cu = 0;
     ADCT_HIP(hipGetDevice(&dev));
     ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -528,7 +605,6 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
         }
     }
     a.band = std::min(band, N - 1);
-    a.P = (a.band + 1) | 1;                 // odd row length: conflict-free LDS columns
     a.step = quant_step;
     a.step_d = double(quant_step);
     a.inv_step = quant_step ? 1.0 / double(quant_step) : 0.0;
@@ -555,6 +631,12 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
     const int nz = n_frames * n_planes;
     hipLaunchKernelGGL(k_jam_zero, dim3((nz + 255) / 256), dim3(256), 0, hs, a.sse, nz);
     ADCT_HIP(hipGetLastError());
-    if (N == 16) return quant_step ? launch<16, true>(a, hs) : launch<16, false>(a, hs);
-    return quant_step ? launch<32, true>(a, hs) : launch<32, false>(a, hs);
+    // kernels for the band of the prefix (rows and columns past it are known
+    // zeros at compile time): N = 16 up to r = 45 and N = 32 up to r = 171, or any r
+    if (N == 16) {
+        if (a.band <= 8) return quant_step ? launch<16, 8, true>(a, hs) : launch<16, 8, false>(a, hs);
+        return quant_step ? launch<16, 15, true>(a, hs) : launch<16, 15, false>(a, hs);
+    }
+    if (a.band <= 17) return quant_step ? launch<32, 17, true>(a, hs) : launch<32, 17, false>(a, hs);
+    return quant_step ? launch<32, 31, true>(a, hs) : launch<32, 31, false>(a, hs);
 }
