@@ -135,3 +135,24 @@ def test_jam_repeat_is_bit_identical(cuda):
     a = _run_image(img, 32, 200, 64, cuda)
     b = _run_image(img, 32, 200, 64, cuda)
     assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_jam_exact_quantiser_ties(cuda, n):
+    """Two-level blocks put B(0, 0) / step and B(0, 1) / step exactly on halves
+    of both signs."""
+    rng = np.random.default_rng(n)
+    nb = 8
+    img = np.zeros((2 * n, nb * n), dtype=np.uint8)
+    for by in range(2):
+        for i in range(nb):
+            a, b = int(rng.integers(0, 128)) * 2 + 1, int(rng.integers(0, 128)) * 2
+            if (by + i) % 2:
+                a, b = b, a
+            img[by * n:(by + 1) * n, i * n:i * n + n // 2] = a
+            img[by * n:(by + 1) * n, i * n + n // 2:(i + 1) * n] = b
+    for r, step in ((2, n), (3, n), (10, 3 * n)):
+        rec, sse, coef = _run_image(img, n, r, step, cuda)
+        want = jam.evaluate(img, TN[n], r, step)
+        assert np.array_equal(coef, want["coef_int"]), (r, step)
+        assert np.array_equal(rec, want["rec"]) and sse == want["sse"], (r, step)

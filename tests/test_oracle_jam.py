@@ -188,3 +188,28 @@ def test_constant_image_any_size(n):
         img = np.full(shape, 77, dtype=np.uint8)
         for r in (1, 3, n * n):
             assert np.array_equal(jam.evaluate(img, jam.jam_n(M.T1, n), r, 0)["rec"], img)
+
+
+def _two_level_blocks(n, seed):
+    """Blocks whose left half is a and right half b (a + b and a - b odd)."""
+    rng = np.random.default_rng(seed)
+    nb = 6
+    a = rng.integers(0, 128, size=nb) * 2 + 1          # odd
+    b = rng.integers(0, 128, size=nb) * 2              # even
+    img = np.zeros((n, nb * n), dtype=np.uint8)
+    for i in range(nb):
+        img[:, i * n:i * n + n // 2] = a[i]
+        img[:, i * n + n // 2:(i + 1) * n] = b[i]
+    return img, a.astype(np.int64), b.astype(np.int64)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_quantiser_ties_round_away_from_zero(n):
+    # B(0, 0) = n (a + b) / 2 and B(0, 1) = n (a - b) / 2 (rows 0 and 1 of T_(n)
+    # are all ones and n/2 ones then n/2 minus ones, both of norm n): with step n
+    # both quotients are exact halves, of either sign
+    img, a, b = _two_level_blocks(n, seed=n)
+    out = jam.evaluate(img, jam.jam_n(M.T1, n), 2, n)
+    away = lambda num: np.sign(num) * ((np.abs(num) + 1) // 2)     # num odd: num / 2 away from 0
+    assert np.array_equal(out["coef_int"][:, 0], away(a + b))
+    assert np.array_equal(out["coef_int"][:, 1], away(a - b))
