@@ -247,7 +247,8 @@ typedef enum { ADCT_SEARCH_CLOSURE = 0, ADCT_SEARCH_CANONICAL = 1 } adct_search_
  * row order, each row k in turn takes the candidate of D = P^8 \ {0} with the
  * smallest angle to DCT row k among those orthogonal to every row chosen so
  * far; an order whose feasible set empties is dead.
- *   P, nP         host: the entry set (distinct values in [-4, 4], must hold 0),
+ *   P, nP         host: the entry set (distinct values in [-8, 8], must hold 0;
+ *                 the extended sets of Sec. 4.1 reach +-8),
  *                 1 <= nP <= 9.  The canonical index of a vector is its
  *                 odometer rank over P ordered 0, 1, -1, 2, -2, ... (first
  *                 coordinate most significant).

@@ -100,17 +100,19 @@ __global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, uint8_t *prim) {
         idx /= b;
     }
     uint32_t lo = 0, hi = 0;
-    bool odd = false, non3 = false;
+    bool odd = false, non3 = false, non5 = false, non7 = false;
     for (int e = 0; e < 8; ++e) {
         const uint32_t byte = uint32_t(uint8_t(int8_t(v[e])));
         if (e < 4) lo |= byte << (8 * e); else hi |= byte << (8 * (e - 4));
         odd |= (v[e] & 1) != 0;
         non3 |= (v[e] % 3) != 0;
+        non5 |= (v[e] % 5) != 0;
+        non7 |= (v[e] % 7) != 0;
     }
     vec[i] = make_uint2(lo, hi);
-    // gcd of the entries is 1 exactly when some entry is odd and some entry is
-    // not a multiple of 3 (entries are within +-4)
-    prim[i] = uint8_t(odd && non3);
+    // gcd of the entries is 1 exactly when no prime divides all of them; the
+    // entries are within +-8, so only 2, 3, 5 and 7 can
+    prim[i] = uint8_t(odd && non3 && non5 && non7);
 }
 
 // ------------------------------------------------------------ greedy queries
@@ -321,7 +323,7 @@ adct_status canonical_digits(const int8_t *P, int nP, int8_t *out, int *b) {
     std::sort(v.begin(), v.end());
     if (std::unique(v.begin(), v.end()) != v.end()) return fail(ADCT_EINVAL, "P has repeated entries");
     for (int x : v)
-        if (x < -4 || x > 4) return fail(ADCT_ERANGE, "entries of P must be within [-4, 4]");
+        if (x < -8 || x > 8) return fail(ADCT_ERANGE, "entries of P must be within [-8, 8]");
     // order 0, 1, -1, 2, -2, ... (the canonical index's digit order)
     std::sort(v.begin(), v.end(), [](int a, int c) {
         const int aa = a < 0 ? -a : a, cc = c < 0 ? -c : c;

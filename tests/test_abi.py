@@ -129,7 +129,7 @@ def test_search_argument_errors_host_only():
     rep = (ctypes.c_int8 * 3)(0, 1, 1)                       # repeated entry
     assert lib.adct_derive_transform(ctypes.cast(rep, ctypes.c_void_p), 3, 0, None, 0, 1, out, 4,
                                      ctypes.byref(n), None, None, None, None) == -1
-    big = (ctypes.c_int8 * 3)(0, 1, 5)                       # entry beyond +-4
+    big = (ctypes.c_int8 * 3)(0, 1, 9)                       # entry beyond +-8
     assert lib.adct_derive_transform(ctypes.cast(big, ctypes.c_void_p), 3, 0, None, 0, 1, out, 4,
                                      ctypes.byref(n), None, None, None, None) == -3
     p1 = (ctypes.c_int8 * 3)(0, 1, -1)

@@ -104,3 +104,65 @@ def test_search_argument_errors(cuda):
         A.derive_transform(S.P1, A.SEARCH_CLOSURE, orders=[[1, 2, 3, 5, 6, 6]])
     with pytest.raises(A.AdctError):
         A.search_topk(S.P1, 0)
+
+
+# ---------------------------------------------------------------- full orders and extended P
+
+EXT_5 = [(0, 1, -1, 4, -4), (0, 1, -1, 8, -8)]
+EXT_7 = [(0, 1, -1, 2, -2, 4, -4), (0, 1, -1, 2, -2, 8, -8), (0, 2, -2, 4, -4, 8, -8)]
+
+
+def test_closure_d1_all_orders(cuda):
+    """All 8! orders with no fixed rows (Sec. 3.5): matrices, leaves and dead paths."""
+    mats, _, leaves, dead = A.derive_transform(S.P1, A.SEARCH_CLOSURE, fix_rows_1_5=False)
+    ref, rleaves, rdead = S.closure(S.P1, orders=None, fixed=None)
+    assert [_key(m) for m in mats] == [_key(m) for m in ref]
+    assert (leaves, dead) == (rleaves, rdead) and leaves >= 40320
+
+
+def test_canonical_d2_full_orders_sampled(cuda):
+    """Per-order canonical results over random full orders of D2 (no fixed rows)."""
+    rng = np.random.default_rng(11)
+    space = S._Space(S.P2)
+    for _ in range(30):
+        o = [int(x) for x in rng.permutation(8)]
+        mats, _, leaves, dead = A.derive_transform(S.P2, A.SEARCH_CANONICAL, orders=[o],
+                                                   fix_rows_1_5=False)
+        ref = S.greedy_canonical(S.P2, o, fixed=None, space=space)
+        if ref is None:
+            assert len(mats) == 0 and dead == 1
+        else:
+            assert len(mats) == 1 and _key(mats[0]) == _key(ref), o
+
+
+@pytest.mark.parametrize("p", EXT_5)
+def test_closure_extended_five_element_sets(cuda, p):
+    """The extended entry sets of Sec. 4.1 with five elements: all 720 orders."""
+    mats, _, leaves, dead = A.derive_transform(p, A.SEARCH_CLOSURE)
+    ref, rleaves, rdead = S.closure(p)
+    assert [_key(m) for m in mats] == [_key(m) for m in ref]
+    assert (leaves, dead) == (rleaves, rdead)
+
+
+@pytest.mark.parametrize("p", EXT_7)
+def test_closure_extended_seven_element_sets_sampled(cuda, p):
+    """The seven-element extended sets (7^8 = 5,764,801 vectors): closure over a
+    sample of orders against the oracle."""
+    rng = np.random.default_rng(10 * len(p) + abs(p[-1]) + abs(p[1]))
+    orders = [tuple(int(x) for x in rng.permutation(list(S.FREE_ROWS))) for _ in range(6)]
+    mats, _, leaves, dead = A.derive_transform(p, A.SEARCH_CLOSURE, orders=[list(o) for o in orders])
+    ref, rleaves, rdead = S.closure(p, orders=orders)
+    assert [_key(m) for m in mats] == [_key(m) for m in ref]
+    assert (leaves, dead) == (rleaves, rdead)
+
+
+def test_topk_extended_set_primitive(cuda):
+    """Top-k over {0, +-1, +-2, +-8} with primitive vectors only (gcd 1 over
+    entries up to 8)."""
+    p = (0, 1, -1, 2, -2, 8, -8)
+    vec, idx, cos = A.search_topk(p, 16, primitive=True)
+    ref = S.topk_scan(p, 16, primitive=True)
+    for r in range(8):
+        assert np.array_equal(idx[r], ref[r]["idx"])
+        assert np.array_equal(vec[r], ref[r]["vec"])
+        np.testing.assert_allclose(cos[r], ref[r]["cos"], rtol=0, atol=1e-15)
