@@ -105,8 +105,46 @@ def other_rows():
     res["search_topk_9pow8_k64"] = {"ms": round(t_scan * 1e3, 2), "candidates": 9 ** 8 - 1,
                                     "rows": 8, "Gcand_rows_per_s": round(8 * (9 ** 8 - 1) / t_scan / 1e9, 2),
                                     "tuples_ms": round(t_tup * 1e3, 2), "orthogonal_tuples": n64}
+    res["search_full_orders_and_extended_P"] = search_wider_row()
     res.update(batch_row())
     return res
+
+
+def search_wider_row():
+    """The searches Sec. 3.5 and 4.1 describe beyond the 720-order runs: all 8!
+    orders with no fixed rows on D1 and D2, and the five extended entry sets
+    (720 orders, rows 1 and 5 fixed).  Matrices are also counted up to positive
+    row scaling (each row divided by the gcd of its entries), which S removes."""
+    import math as _m
+
+    import numpy as np
+
+    import paper_1808_02950_amd as A
+
+    def primitive_count(mats):
+        keys = set()
+        for t in mats:
+            rows = []
+            for r in np.asarray(t, dtype=np.int64):
+                g = 0
+                for v in r:
+                    g = _m.gcd(g, int(v))
+                rows.append(tuple(int(v) // max(g, 1) for v in r))
+            keys.add(tuple(rows))
+        return len(keys)
+
+    out = {}
+    runs = [("D1_all_8!_orders", [0, 1, -1], False), ("D2_all_8!_orders", [0, 1, -1, 2, -2], False)]
+    runs += [("P_" + "_".join(str(v) for v in p if v > 0) + "_720_orders", p, True)
+             for p in ([0, 1, -1, 4, -4], [0, 1, -1, 8, -8], [0, 1, -1, 2, -2, 4, -4],
+                       [0, 1, -1, 2, -2, 8, -8], [0, 2, -2, 4, -4, 8, -8])]
+    for name, p, fix in runs:
+        t0 = time.perf_counter()
+        mats, _, leaves, dead = A.derive_transform(p, A.SEARCH_CLOSURE, fix_rows_1_5=fix)
+        out[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "space": len(p) ** 8 - 1,
+                     "matrices": int(len(mats)), "up_to_row_scaling": primitive_count(mats),
+                     "leaves": leaves, "dead_paths": dead}
+    return out
 
 
 def batch_row():

@@ -120,3 +120,70 @@ def test_topk_small_space_brute_force():
         order = S.canonical_order(cos, np.sum(d * d, axis=1), idx)[:20]
         assert np.array_equal(res[row]["idx"], idx[order])
     assert np.array_equal(res[2]["vec"][0], M.T1[2])
+
+
+def _brute_greedy_ok(p, order, t):
+    """Check a full-order greedy result by plain loops: every row is orthogonal
+    to the rows chosen before it, and no vector of P^8 orthogonal to them has a
+    strictly larger cosine to its DCT row (beyond the tie tolerance)."""
+    import itertools
+    c = M.dct_matrix()
+    chosen = []
+    for k in order:
+        best = -2.0
+        for v in itertools.product(p, repeat=8):
+            if not any(v):
+                continue
+            if any(sum(a * b for a, b in zip(v, u)) for u in chosen):
+                continue
+            cs = sum(a * b for a, b in zip(v, c[k])) / math.sqrt(sum(a * a for a in v))
+            best = max(best, cs)
+        row = [int(x) for x in t[k]]
+        if any(sum(a * b for a, b in zip(row, u)) for u in chosen):
+            return False
+        got = sum(a * b for a, b in zip(row, c[k])) / math.sqrt(sum(a * a for a in row))
+        if got < best - S.TIE_EPS:
+            return False
+        chosen.append(row)
+    return True
+
+
+def test_full_order_greedy_by_brute_force():
+    """All eight rows free (the 8! orders of Sec. 3.5): a few orders on D1
+    checked against exhaustive loops."""
+    rng = np.random.default_rng(5)
+    space = S._Space(S.P1)
+    for _ in range(3):
+        o = [int(x) for x in rng.permutation(8)]
+        t = S.greedy_canonical(S.P1, o, fixed=None, space=space)
+        assert t is not None and _brute_greedy_ok(S.P1, o, t)
+
+
+def test_full_order_closure_d1_is_rdct_and_t4():
+    """Without fixed rows the closure over all 40,320 orders on D1 reaches the
+    same two matrices as the 720-order search of Sec. 4.1."""
+    mats, leaves, dead = S.closure(S.P1, orders=None, fixed=None)
+    keys = sorted(np.asarray(m, dtype=np.int8).tobytes() for m in mats)
+    assert keys == sorted(np.asarray(m, dtype=np.int8).tobytes() for m in (M.T_RDCT, M.T4))
+    assert leaves >= 40320 and dead == 0
+
+
+@pytest.mark.parametrize("p", [(0, 1, -1, 4, -4), (0, 1, -1, 8, -8)])
+def test_extended_sets_do_not_beat_t1(p):
+    """Sec. 4.1: the extended entry sets gave matrices that performed worse than
+    the proposed ones at a higher cost.  For the five-element sets: every matrix
+    of the 720-order closure has a lower coding gain and transform efficiency
+    than T1, and more additions and more non-trivial multiplications (entries
+    other than 0 and +-1) in direct form."""
+    mats, leaves, dead = S.closure(p)
+    assert len(mats) >= 1 and leaves == 720
+    ref = Me.measures(M.T1)
+
+    def cost(t):
+        t = np.asarray(t)
+        return (int(sum(max(np.count_nonzero(r) - 1, 0) for r in t)),
+                int(np.count_nonzero(np.abs(t) > 1)))
+    for t in mats:
+        m = Me.measures(t)
+        assert m["cg_star"] < ref["cg_star"] and m["eta"] < ref["eta"]
+        assert cost(t)[0] > cost(M.T1)[0] and cost(t)[1] > cost(M.T1)[1]
