@@ -17,6 +17,7 @@ Modules
   postfilter  float64 conv network forward/backward on bfloat16-rounded operands
   ssim      structural similarity of a reconstruction (Gaussian-window local statistics)
   jam       16- and 32-point matrices by the JAM construction; N x N transform coding
+  nonortho  inverse decoder for non-orthogonal matrices (SDCT, BAS-2008b); coding gain vs correlation
 
 Every function cites the passage of the paper it restates.  Readings taken where
 the paper is silent or ambiguous are stated where they are used.
