@@ -233,6 +233,41 @@ adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t frame_stride
                                      int32_t *coef, uint8_t *recon, int64_t frame_stride_out,
                                      uint64_t *sse, adct_stream_t stream);
 
+/* ---------------------------------------------------------------- non-orthogonal matrices */
+
+/* Zonal transform coding with an invertible integer matrix T whose rows need
+ * not be orthogonal (the signed DCT and BAS-2008b among the paper's
+ * competitors, Sec. 2 and 4.3): per 8x8 block B = C_hat A C_hat^T with
+ * C_hat = S T, S = diag(1/sqrt(diag(T T^T))), the first r zig-zag coefficients
+ * kept, and the inverse decoder A = C_hat^-1 B' C_hat^-T (the transpose inverse
+ * of Sec. 6.1.1 holds for orthogonal rows only), rounded half to even and
+ * clipped; squared errors per (frame, plane).  The reconstruction equals
+ * adj(T) Y' adj(T)^T / det(T)^2 with Y' the kept integer stage and is computed
+ * exactly.  frames / planes / recon / frame strides as in adct_evaluate_stream
+ * (H, W multiples of 8).  T: host int8 [64] row-major.  sse: device uint64
+ * [n_frames][n_planes], 8-byte aligned, zeroed by the call then accumulated;
+ * recon nullable.  No quantiser (the paper's image experiment is zonal).
+ * Errors: ADCT_EINVAL null frames / planes / T / sse, T singular; ADCT_ERANGE r
+ * not in [1, 64], n_frames < 1, n_planes not in [1, 4], too many blocks;
+ * ADCT_EDIM a plane not a positive multiple of 8, pitch < W, negative offset,
+ * unaligned sse, non-positive frame stride with several frames; ADCT_EOVERFLOW
+ * T whose exact numerators would pass 2^53. */
+adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                  const adct_plane *planes, int n_planes, const int8_t *T, int r,
+                                  uint8_t *recon, int64_t frame_stride_out, uint64_t *sse,
+                                  adct_stream_t stream);
+
+/* Unified coding gain C_g* (Sec. 4.2.3) of n_t real 8x8 matrices C_hat at n_rho
+ * correlations of the first-order Markov model, R_x[i][j] = rho^|i-j| (the curve
+ * of Sec. 4.3 is its difference to the exact DCT's): 10 sum_i -log10(A_i B_i)/8,
+ * A_i = sum_jk c_ij c_ik rho^|j-k|, B_i the squared norm of row i of C_hat^-1.
+ * c_hat: host double [n_t][64] row-major; rho: host double [n_rho] in [0, 1);
+ * cg_out: host double [n_t][n_rho] (dB).  Synchronises `stream`; allocates and
+ * frees its own device buffers.  Errors: ADCT_EINVAL null; ADCT_ERANGE counts
+ * below 1, n_t * n_rho > 2^26, rho outside [0, 1). */
+adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, const double *rho, int n_rho,
+                                   double *cg_out, adct_stream_t stream);
+
 /* ---------------------------------------------------------------- search */
 
 /* Search modes of adct_derive_transform (Sec. 3.5 and 4.1).  Exact ties in

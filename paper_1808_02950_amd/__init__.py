@@ -66,6 +66,8 @@ _SIGNATURES = {
                                   ctypes.POINTER(Matrix), _I, _I, _P, _P, _I64, _P, _P]),
     "adct_ssim": (_I, [_P, _I64, _P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _P]),
     "adct_jam_matrix": (_I, [_I, _I, _P, _P]),
+    "adct_evaluate_inverse": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _I, _P, _I64, _P, _P]),
+    "adct_coding_gain_sweep": (_I, [_P, _I, _P, _I, _P, _P]),
     "adct_jam_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I, _I, _I, _I,
                                       _P, _P, _I64, _P, _P]),
     "adct_derive_transform": (_I, [_P, _I, _I, _P, _I, _I, ctypes.POINTER(Matrix), _I,
@@ -328,6 +330,45 @@ def jam_evaluate_stream(frames, planes, n: int, r: int, quant_step: int = 0, coe
                                           recon.stride(0) if recon is not None else 0,
                                           _ptr(sse), _stream(stream)))
     return sse
+
+
+def evaluate_inverse(frames, planes, T, r: int, recon=None, sse=None, stream=None):
+    """adct_evaluate_inverse: zonal coding with an invertible (not necessarily
+    orthogonal) int8 matrix T (8, 8) and the inverse decoder.  frames: uint8 CUDA
+    tensor (n_frames, frame_bytes); planes: list of (offset, H, W, pitch).
+    Returns the device SSE tensor (n_frames, n_planes); does not synchronise."""
+    import torch
+    _need_cuda(frames, torch.uint8, "frames")
+    nf = frames.shape[0]
+    for name, buf in (("frames", frames), ("recon", recon)):
+        if buf is None:
+            continue
+        if buf.dim() != 2 or buf.stride(1) != 1 or buf.shape[0] != nf:
+            raise ValueError(f"{name} must be (n_frames, frame_bytes) with unit inner stride")
+        for off, h, w, pitch in planes:
+            if off + (h - 1) * pitch + w > buf.shape[1]:
+                raise ValueError(f"a plane reaches past the end of a frame of {name}")
+    if recon is not None:
+        _need_cuda(recon, torch.uint8, "recon")
+    t = np.ascontiguousarray(np.asarray(T, dtype=np.int8).reshape(64))
+    if sse is None:
+        sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
+    arr = planes_struct(planes)
+    _check(lib().adct_evaluate_inverse(_ptr(frames), frames.stride(0), nf, arr, len(planes), t.ctypes.data,
+                                       r, _ptr(recon), recon.stride(0) if recon is not None else 0,
+                                       _ptr(sse), _stream(stream)))
+    return sse
+
+
+def coding_gain_sweep(c_hats, rhos, stream=None):
+    """adct_coding_gain_sweep: unified coding gain (dB) of each real 8x8 matrix
+    at each correlation.  Returns numpy (n_t, n_rho)."""
+    c = np.ascontiguousarray(np.asarray(c_hats, dtype=np.float64).reshape(-1, 64))
+    r = np.ascontiguousarray(np.asarray(rhos, dtype=np.float64).reshape(-1))
+    out = np.zeros((c.shape[0], r.shape[0]), dtype=np.float64)
+    _check(lib().adct_coding_gain_sweep(c.ctypes.data, c.shape[0], r.ctypes.data, r.shape[0],
+                                        out.ctypes.data, _stream(stream)))
+    return out
 
 
 def stream_blocks_per_frame(planes) -> int:

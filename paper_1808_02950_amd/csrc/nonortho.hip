@@ -1,0 +1,362 @@
+// Non-orthogonal low-complexity matrices (the signed DCT, BAS-2008b, any
+// invertible integer T) on gfx950, and the unified coding gain against the
+// inter-pixel correlation (Sec. 2, 4.2.3, 4.3, 6.1.1).
+//
+// Decoder: for T without orthogonal rows the transpose is no inverse, and the
+// reconstruction is A = C_hat^-1 B' C_hat^-T.  With C_hat = S T (S diagonal) and
+// zonal coding B' = S Y' S, this is T^-1 Y' T^-T = adj(T) Y' adj(T)^T / det(T)^2:
+// the kernel computes the numerator in float64 on integers (exact below 2^53,
+// bounded on the host) and divides exactly, so the pixels are bit-exact.
+// One lane owns one 8x8 block for the whole pipeline.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "adct_internal.hpp"
+
+namespace adct {
+namespace {
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+struct InvPlane {
+    int64_t off;
+    int32_t pitch, nbx, nblocks, wave_start;
+};
+
+struct InvArgs {
+    const uint8_t *in;
+    uint8_t *out;
+    unsigned long long *sse;
+    int64_t fs_in, fs_out;
+    int32_t n_frames, n_planes, waves_per_frame, r;
+    int32_t T[64];         // T[8k + m]
+    double adj[64];        // adj(T)[8x + k]
+    double den;            // det(T)^2
+    double inv_den;
+    InvPlane pl[kMaxPlanes];
+};
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// round-half-to-even(n / den) clipped to [0, 255]; n and den integers held
+// exactly in doubles
+__device__ __forceinline__ int rne_div_exact(double n, double den, double inv_den) {
+    const double c = fmin(fmax(n, 0.0), 255.0 * den);
+    double q = floor(c * inv_den);
+    double rem = c - q * den;
+    if (rem < 0.0) { q -= 1.0; rem += den; }
+    if (rem >= den) { q += 1.0; rem -= den; }
+    const int qi = int(q);
+    const double twice = rem + rem;
+    return qi + ((twice > den || (twice == den && (qi & 1))) ? 1 : 0);
+}
+
+__global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int total = a.n_frames * a.waves_per_frame;
+    unsigned long long acc = 0;
+    int acc_fp = -1;
+    for (int gw = int(blockIdx.x) * 4 + int(threadIdx.x >> 6); gw < total; gw += int(gridDim.x) * 4) {
+        const int f = gw / a.waves_per_frame;
+        const int w = gw - f * a.waves_per_frame;
+        int p = 0;
+        while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
+        const InvPlane &P = a.pl[p];
+        const int blk = (w - P.wave_start) * 64 + lane;
+        const bool active = blk < P.nblocks;
+        const int b = active ? blk : 0;
+        const int by = b / P.nbx, bx = b - (b / P.nbx) * P.nbx;
+        const int64_t off = P.off + int64_t(8 * by) * P.pitch + 8 * bx;
+        const uint8_t *src = a.in + int64_t(f) * a.fs_in + off;
+        uint32_t pix[8][2];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const u32x2 v = *(const u32x2 *)(src + int64_t(x) * P.pitch);
+            pix[x][0] = v.x;
+            pix[x][1] = v.y;
+        }
+        // Y = T A T^T, then the zig-zag prefix
+        int Z[8][8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                int s = 0;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) s += a.T[8 * l + m] * int((pix[x][m >> 2] >> (8 * (m & 3))) & 0xffu);
+                Z[x][l] = s;
+            }
+        int Y[8][8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                int s = 0;
+#pragma unroll
+                for (int x = 0; x < 8; ++x) s += a.T[8 * k + x] * Z[x][l];
+                Y[k][l] = (zz_pos(k, l) < a.r) ? s : 0;
+            }
+        // numerator adj Y' adj^T row by row (integers, exact in float64); the
+        // row loop stays rolled (one row's sums live at a time) and re-reads the
+        // row's pixels for the error
+        unsigned e = 0;
+        uint8_t *dst = a.out ? a.out + int64_t(f) * a.fs_out + off : nullptr;
+#pragma unroll 1
+        for (int x = 0; x < 8; ++x) {
+            const u32x2 px = *(const u32x2 *)(src + int64_t(x) * P.pitch);
+            double U[8];
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s = fma(a.adj[8 * x + k], double(Y[k][l]), s);
+                U[l] = s;
+            }
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int y = 0; y < 8; ++y) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < 8; ++l) s = fma(U[l], a.adj[8 * y + l], s);
+                const int q = rne_div_exact(s, a.den, a.inv_den);
+                const int d = q - int(((y < 4 ? px.x : px.y) >> (8 * (y & 3))) & 0xffu);
+                e += unsigned(d * d);
+                if (y < 4) lo |= uint32_t(q) << (8 * y); else hi |= uint32_t(q) << (8 * (y - 4));
+            }
+            if (active && dst) {
+                u32x2 v;
+                v.x = lo;
+                v.y = hi;
+                *(u32x2 *)(dst + int64_t(x) * P.pitch) = v;
+            }
+        }
+        if (!active) e = 0;
+        const int fp = f * a.n_planes + p;
+        if (fp != acc_fp) {
+            if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
+            acc = 0;
+            acc_fp = fp;
+        }
+        acc += wave_sum(e);
+    }
+    if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
+}
+
+__global__ void k_inv_zero(unsigned long long *p, int n) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0ull;
+}
+
+// ------------------------------------------------------------------ coding gain
+
+// C_g*(C_hat, rho) = 10 sum_i -log10(A_i B_i) / 8 with A_i = sum_jk c_ij c_ik
+// rho^|j - k| and B_i the squared norm of row i of C_hat^-1 (Sec. 4.2.3).  One
+// thread per (matrix, rho); the inverse by Gauss-Jordan with partial pivoting.
+__global__ void k_coding_gain(const double *c_hat, int n_t, const double *rho, int n_rho, double *out) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n_t * n_rho) return;
+    const int t = i / n_rho, j = i - t * n_rho;
+    const double *c = c_hat + 64 * t;
+    double m[8][16];
+    for (int r = 0; r < 8; ++r)
+        for (int q = 0; q < 16; ++q) m[r][q] = q < 8 ? c[8 * r + q] : (q - 8 == r ? 1.0 : 0.0);
+    for (int col = 0; col < 8; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 8; ++r)
+            if (fabs(m[r][col]) > fabs(m[piv][col])) piv = r;
+        if (piv != col)
+            for (int q = 0; q < 16; ++q) {
+                const double tmp = m[col][q];
+                m[col][q] = m[piv][q];
+                m[piv][q] = tmp;
+            }
+        const double inv = 1.0 / m[col][col];
+        for (int q = 0; q < 16; ++q) m[col][q] *= inv;
+        for (int r = 0; r < 8; ++r) {
+            if (r == col) continue;
+            const double fct = m[r][col];
+            for (int q = 0; q < 16; ++q) m[r][q] -= fct * m[col][q];
+        }
+    }
+    double pw[8];
+    pw[0] = 1.0;
+    for (int d = 1; d < 8; ++d) pw[d] = pw[d - 1] * rho[j];
+    double total = 0.0;
+    for (int r = 0; r < 8; ++r) {
+        double A = 0.0, B = 0.0;
+        for (int x = 0; x < 8; ++x)
+            for (int y = 0; y < 8; ++y) A += c[8 * r + x] * c[8 * r + y] * pw[x > y ? x - y : y - x];
+        for (int q = 0; q < 8; ++q) B += m[r][8 + q] * m[r][8 + q];
+        total += -log10(A * B) / 8.0;
+    }
+    out[i] = 10.0 * total;
+}
+
+// exact determinant of an n x n integer matrix (n <= 8) by fraction-free
+// (Bareiss) elimination: every division is exact
+__int128 bareiss_det(__int128 (*m)[8], int n) {
+    __int128 prev = 1;
+    int sign = 1;
+    for (int k = 0; k < n - 1; ++k) {
+        if (m[k][k] == 0) {
+            int r = k + 1;
+            while (r < n && m[r][k] == 0) ++r;
+            if (r == n) return 0;
+            for (int q = 0; q < n; ++q) std::swap(m[k][q], m[r][q]);
+            sign = -sign;
+        }
+        for (int i = k + 1; i < n; ++i)
+            for (int j = k + 1; j < n; ++j) m[i][j] = (m[i][j] * m[k][k] - m[i][k] * m[k][j]) / prev;
+        prev = m[k][k];
+    }
+    return sign * m[n - 1][n - 1];
+}
+
+// adj(T) (the transposed cofactor matrix, adj(T) T = det(T) I) and det(T):
+// 0 on success, 1 when T is singular, 2 when an entry reaches 2^53
+int adjugate_det(const int8_t *T, int64_t adj[64], int64_t *det) {
+    const __int128 lim = __int128(1) << 53;
+    __int128 m[8][8];
+    for (int r = 0; r < 8; ++r)
+        for (int q = 0; q < 8; ++q) m[r][q] = T[8 * r + q];
+    const __int128 d = bareiss_det(m, 8);
+    if (d == 0) return 1;
+    if (d >= lim || d <= -lim) return 2;
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) {
+            // cofactor C_ji: delete row j and column i
+            __int128 mm[8][8];
+            for (int r = 0, rr = 0; r < 8; ++r) {
+                if (r == j) continue;
+                for (int q = 0, qq = 0; q < 8; ++q) {
+                    if (q == i) continue;
+                    mm[rr][qq++] = T[8 * r + q];
+                }
+                ++rr;
+            }
+            const __int128 c = bareiss_det(mm, 7);
+            if (c >= lim || c <= -lim) return 2;
+            adj[8 * i + j] = int64_t(((i + j) & 1) ? -c : c);
+        }
+    *det = int64_t(d);
+    return 0;
+}
+
+}  // namespace
+}  // namespace adct
+
+using namespace adct;
+
+extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                             const adct_plane *planes, int n_planes, const int8_t *T, int r,
+                                             uint8_t *recon, int64_t frame_stride_out, uint64_t *sse,
+                                             adct_stream_t stream) {
+    if (!frames || !planes || !T || !sse) return fail(ADCT_EINVAL, "frames, planes, T and sse are required");
+    if (r < 1 || r > 64) return fail(ADCT_ERANGE, "r must be in [1, 64]");
+    if (n_frames < 1) return fail(ADCT_ERANGE, "n_frames must be >= 1");
+    if (n_planes < 1 || n_planes > kMaxPlanes) return fail(ADCT_ERANGE, "n_planes must be in [1, 4]");
+    if (n_frames > 1 && (frame_stride <= 0 || (recon && frame_stride_out <= 0)))
+        return fail(ADCT_EDIM, "frame strides must be positive for several frames");
+    if (reinterpret_cast<uintptr_t>(sse) & 7) return fail(ADCT_EDIM, "sse must be 8-byte aligned");
+    InvArgs a;
+    memset(&a, 0, sizeof(a));
+    int64_t adj[64], det = 0;
+    const int ad = adjugate_det(T, adj, &det);
+    if (ad == 1) return fail(ADCT_EINVAL, "T is singular");
+    if (ad == 2) return fail(ADCT_EOVERFLOW, "T is too large for exact float64 numerators");
+    // numerator bound: |adj Y' adj^T| <= (sum |adj|)^2 max|Y| per entry
+    int64_t rowsum = 0, tsum = 0;
+    for (int k = 0; k < 8; ++k) {
+        int64_t s = 0, u = 0;
+        for (int m = 0; m < 8; ++m) {
+            s += std::abs(int64_t(T[8 * k + m]));
+            u += std::abs(adj[8 * k + m]);
+        }
+        tsum = std::max(tsum, s);
+        rowsum = std::max(rowsum, u);
+    }
+    const double ymax = 255.0 * double(tsum) * double(tsum);
+    if (double(rowsum) * double(rowsum) * ymax >= 9.0e15 || double(det) * double(det) >= 9.0e15 ||
+        ymax * 8 >= 2.0e9)
+        return fail(ADCT_EOVERFLOW, "T is too large for exact float64 numerators");
+    for (int i = 0; i < 64; ++i) {
+        a.T[i] = T[i];
+        a.adj[i] = double(adj[i]);
+    }
+    a.den = double(det) * double(det);
+    a.inv_den = 1.0 / a.den;
+    a.in = frames;
+    a.out = recon;
+    a.sse = reinterpret_cast<unsigned long long *>(sse);
+    a.fs_in = frame_stride;
+    a.fs_out = frame_stride_out;
+    a.n_frames = n_frames;
+    a.n_planes = n_planes;
+    a.r = r;
+    int64_t waves = 0;
+    for (int p = 0; p < n_planes; ++p) {
+        const adct_plane &q = planes[p];
+        if (q.H < 8 || q.W < 8 || (q.H & 7) || (q.W & 7) || q.pitch < q.W || q.offset < 0)
+            return fail(ADCT_EDIM, "each plane needs H, W positive multiples of 8, pitch >= W, offset >= 0");
+        InvPlane &d = a.pl[p];
+        d.off = q.offset;
+        d.pitch = q.pitch;
+        d.nbx = q.W / 8;
+        d.nblocks = (q.H / 8) * (q.W / 8);
+        d.wave_start = int32_t(waves);
+        waves += (d.nblocks + 63) / 64;
+        if (waves > (int64_t(1) << 30)) return fail(ADCT_ERANGE, "planes too large");
+    }
+    if (waves * n_frames > (int64_t(1) << 31) - 1) return fail(ADCT_ERANGE, "too many blocks in one call");
+    a.waves_per_frame = int32_t(waves);
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const int nz = n_frames * n_planes;
+    hipLaunchKernelGGL(k_inv_zero, dim3((nz + 255) / 256), dim3(256), 0, hs, a.sse, nz);
+    ADCT_HIP(hipGetLastError());
+    int dev = 0, cus = 0, per_cu = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_inverse_codec, 256, 0));
+    const int64_t want = (waves * n_frames + 3) / 4;
+    const int grid = int(std::min<int64_t>(want, int64_t(std::max(per_cu, 1)) * cus));
+    hipLaunchKernelGGL(k_inverse_codec, dim3(grid), dim3(256), 0, hs, a);
+    ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
+}
+
+extern "C" adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, const double *rho, int n_rho,
+                                              double *cg_out, adct_stream_t stream) {
+    if (!c_hat || !rho || !cg_out) return fail(ADCT_EINVAL, "c_hat, rho and cg_out are required");
+    if (n_t < 1 || n_rho < 1 || int64_t(n_t) * n_rho > (int64_t(1) << 26))
+        return fail(ADCT_ERANGE, "n_t and n_rho must be >= 1, n_t * n_rho <= 2^26");
+    for (int j = 0; j < n_rho; ++j)
+        if (!(rho[j] >= 0.0 && rho[j] < 1.0)) return fail(ADCT_ERANGE, "rho must be in [0, 1)");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const size_t nc = size_t(n_t) * 64, no = size_t(n_t) * n_rho;
+    double *dc = nullptr, *dr = nullptr, *dout = nullptr;
+    adct_status st = ADCT_OK;
+    hipError_t e = hipMalloc(&dc, nc * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&dr, size_t(n_rho) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&dout, no * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, c_hat, nc * sizeof(double), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(dr, rho, size_t(n_rho) * sizeof(double), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_coding_gain, dim3(unsigned((no + 255) / 256)), dim3(256), 0, hs, dc, n_t, dr, n_rho,
+                           dout);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(cg_out, dout, no * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) st = hip_fail(e, "coding gain sweep");
+    if (dc) (void)hipFree(dc);
+    if (dr) (void)hipFree(dr);
+    if (dout) (void)hipFree(dout);
+    return st;
+}

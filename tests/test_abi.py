@@ -246,3 +246,41 @@ def test_jam_argument_errors_host_only():
     assert call(planes=A.planes_struct([(-1, 40, 40, 40)])) == -2
     assert call(sse=ctypes.c_void_p(8196)) == -2
     assert call(coef=ctypes.c_void_p(4098)) == -2
+
+
+def test_inverse_codec_argument_errors_host_only():
+    """adct_evaluate_inverse validates every argument before it launches anything."""
+    lib = A.lib()
+    FAKE = ctypes.c_void_p(4096)
+    SSE = ctypes.c_void_p(8192)
+    ok = A.planes_struct([(0, 16, 16, 16)])
+    good = (ctypes.c_int8 * 64)(*[int(v) for v in np.sign(np.cos(np.outer(np.arange(8), 2 * np.arange(8) + 1)
+                                                                   * np.pi / 16)).ravel()])
+    sing = (ctypes.c_int8 * 64)(*([1] * 64))
+
+    def call(frames=FAKE, nf=1, planes=ok, npl=1, T=good, r=10, sse=SSE, fs=0):
+        return lib.adct_evaluate_inverse(frames, fs, nf, planes, npl, ctypes.cast(T, ctypes.c_void_p) if T else None,
+                                         r, None, 0, sse, None)
+    assert call(frames=None) == -1 and call(T=None) == -1 and call(sse=None) == -1
+    assert call(T=sing) == -1
+    assert call(r=0) == -3 and call(r=65) == -3
+    assert call(nf=0) == -3 and call(npl=0) == -3 and call(npl=5) == -3
+    assert call(planes=A.planes_struct([(0, 12, 16, 16)])) == -2
+    assert call(planes=A.planes_struct([(0, 16, 16, 8)])) == -2
+    assert call(sse=ctypes.c_void_p(8196)) == -2
+    assert call(nf=2, fs=0) == -2
+    h = np.array([[1]])
+    for _ in range(3):
+        h = np.block([[h, h], [h, -h]])                        # 8 x 8 Hadamard
+    big = (ctypes.c_int8 * 64)(*[int(v) for v in (120 * h).ravel()])
+    assert call(T=big) == -4
+
+
+def test_coding_gain_argument_errors_host_only():
+    lib = A.lib()
+    c = np.eye(8).ravel()
+    rho = np.array([0.5, 1.0])
+    out = np.zeros(2)
+    assert lib.adct_coding_gain_sweep(None, 1, rho.ctypes.data, 1, out.ctypes.data, None) == -1
+    assert lib.adct_coding_gain_sweep(c.ctypes.data, 0, rho.ctypes.data, 1, out.ctypes.data, None) == -3
+    assert lib.adct_coding_gain_sweep(c.ctypes.data, 1, rho.ctypes.data, 2, out.ctypes.data, None) == -3
