@@ -106,6 +106,7 @@ def other_rows():
                                     "rows": 8, "Gcand_rows_per_s": round(8 * (9 ** 8 - 1) / t_scan / 1e9, 2),
                                     "tuples_ms": round(t_tup * 1e3, 2), "orthogonal_tuples": n64}
     res["search_full_orders_and_extended_P"] = search_wider_row()
+    res["coding_gain_vs_rho"] = coding_gain_row()
     res.update(batch_row())
     return res
 
@@ -198,7 +199,21 @@ def batch_row():
                 vals.append(A.ssim(img, rec, None))
             curve[t].append(round(float(torch.cat(vals).mean().item()), 6))
     ssim_s = time.perf_counter() - t0
-    return {"batch_45img_6tf_r1_63": {
+    # non-orthogonal competitors with the inverse decoder on the same images
+    # (per image; T1 through the same decoder for reference)
+    comp = {"SDCT": sdct_matrix(), "BAS2008B": BAS2008B, "T1": A.matrix_get("T1")}
+    nonortho = {}
+    for name, t in comp.items():
+        nonortho[name] = []
+        for r in (4, 10, 20, 40):
+            vals = []
+            for (o, h, w, _) in planes:
+                s_ = A.evaluate_inverse(base[o:o + h * w].view(1, -1), [(0, h, w, w)], t, r)
+                vals.append(s_)
+            s_all = torch.cat(vals).cpu().numpy().ravel()
+            nonortho[name].append(round(float(np.mean(10 * np.log10(255.0 ** 2 * npix / np.maximum(s_all, 1)))), 4))
+    return {"nonortho_competitors_45img_psnr": {"r": [4, 10, 20, 40], **nonortho},
+            "batch_45img_6tf_r1_63": {
         "ms": round(ms, 3), "evaluations": evals, "evaluations_per_s": round(evals / (ms / 1e3)),
         "Gpixel_evals_per_s": round(off * len(names) * 63 / (ms / 1e3) / 1e9, 1),
         "pixels": off, "schedule": info,
@@ -206,6 +221,55 @@ def batch_row():
         "ssim_vs_r_45img": {"r": rs, **curve,
                             "T1_above_DCT_at_r": [r for r, a, b in zip(rs, curve["T1"], curve["DCT"]) if a > b],
                             "seconds": round(ssim_s, 2)}}
+
+
+# BAS-2008b as printed in the paper's table of low-complexity matrices (Sec. 2);
+# the signed DCT is sgn(C) entrywise (Sec. 2).  Inputs of the competitor rows.
+BAS2008B = [[1, 1, 1, 1, 1, 1, 1, 1], [1, 1, 1, 0, 0, -1, -1, -1], [1, 1, -1, -1, -1, -1, 1, 1],
+            [1, 0, -1, 0, 0, 1, 0, -1], [1, -1, -1, 1, 1, -1, -1, 1], [1, -1, 1, 0, 0, -1, 1, -1],
+            [1, -1, 1, -1, -1, 1, -1, 1], [1, -1, 1, -1, 1, -1, 1, -1]]
+
+
+def dct_rows():
+    """Orthonormal 8-point DCT-II from its closed form."""
+    import numpy as np
+    k = np.arange(8)[:, None]
+    n = np.arange(8)[None, :]
+    c = np.cos((2 * n + 1) * k * np.pi / 16) / 2.0
+    c[0] = 1 / np.sqrt(8.0)
+    return c
+
+
+def sdct_matrix():
+    import numpy as np
+    return np.sign(dct_rows()).astype(np.int8)
+
+
+def coding_gain_row():
+    """Coding-gain loss against the exact DCT over 0 < rho < 1 (Sec. 4.3's figure)
+    for T1, LO, T6 and the two non-orthogonal competitors, one GPU launch."""
+    import numpy as np
+
+    import paper_1808_02950_amd as A
+
+    def chat(t):
+        t = np.asarray(t, dtype=np.float64)
+        return t / np.sqrt((t * t).sum(axis=1))[:, None]
+
+    names = ["T1", "LO", "T6"]
+    mats = [dct_rows()] + [chat(A.matrix_get(n)) for n in names] + [chat(sdct_matrix()), chat(BAS2008B)]
+    names += ["SDCT", "BAS2008B"]
+    rhos = np.linspace(0.001, 0.999, 999)
+    A.coding_gain_sweep(np.stack(mats), rhos)
+    t0 = time.perf_counter()
+    cg = A.coding_gain_sweep(np.stack(mats), rhos)
+    ms = (time.perf_counter() - t0) * 1e3
+    d = cg[1:] - cg[0]
+    i95 = int(np.argmin(np.abs(rhos - 0.95)))
+    return {"ms": round(ms, 3), "matrices": len(mats), "rho_points": len(rhos),
+            "loss_dB_at_rho_0.95": {n: round(float(d[i, i95]), 4) for i, n in enumerate(names)},
+            "T1_smallest_loss_every_rho": bool(np.all(np.abs(d[0]) < np.abs(d[1:]).min(axis=0))),
+            "T1_over_LO_loss_at_0.95": round(float(d[0, i95] / d[1, i95]), 3)}
 
 
 FILTER_FLOP_PER_PX = 2 * (9 * 32 + 288 * 32 + 288)   # 19,584: forward MACs x 2, per output pixel
@@ -463,6 +527,19 @@ def main():
             "psnr_frame_mean": round(pj, 4), "ssim_frame_mean": round(frame_ssim(sj), 6)}
     A.evaluate_stream(frames, planes, "T1", r, 32, sse=sse_j)
     jam["T1_8x8_r10_q32_psnr_frame_mean"] = round(psnrs(sse_j)[0], 4)
+
+    # the inverse decoder (non-orthogonal matrices) on the same stream, SDCT, r = 10
+    A.evaluate_inverse(frames, planes, sdct_matrix(), r, recon=recon_j, sse=sse_j)
+    torch.cuda.synchronize()
+    ev2.record()
+    for _ in range(dct_steps):
+        A.evaluate_inverse(frames, planes, sdct_matrix(), r, recon=recon_j, sse=sse_j)
+    ev3.record()
+    torch.cuda.synchronize()
+    inv_ms = ev2.elapsed_time(ev3) / dct_steps
+    inverse_row = {"kernel_ms": round(inv_ms, 4), "GB_per_s": round(2 * samples / (inv_ms / 1e3) / 1e9, 1),
+                   "hbm_frac": round(2 * samples / (inv_ms / 1e3) / 1e9 / peak, 4),
+                   "psnr_frame_mean_SDCT_r10": round(psnrs(sse_j)[0], 4)}
     jam["T1_8x8_r10_q16_psnr_frame_mean"] = round(psnr_frame, 4)
 
     out = {
@@ -500,6 +577,7 @@ def main():
                  "kernel_ms": round(ssim_ms, 3), "fp64_tflops": round(ssim_flop / (ssim_ms / 1e3) / 1e12, 1),
                  "peak_fp64_tflops": 78.6},
         "jam_16_32_point": jam,
+        "inverse_decoder_SDCT": inverse_row,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
                      "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
