@@ -410,8 +410,10 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
     acc += wave_sum(e);
 }
 
+// The 16-point narrow-band kernel is held to 128 VGPRs (4 waves per SIMD; a few
+// bytes spill), which pays; the others would spill heavily.
 template <int N, int BAND, bool QUANT>
-__global__ __launch_bounds__(64) void k_jam(const JamArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N == 16 && BAND <= 8 ? 4 : 1, 8))) void k_jam(const JamArgs a) {
     constexpr int NW = N / 4;
     constexpr int P = (BAND + 1) | 1;
     // two LDS areas, so that the column pass can store its inverse while other
