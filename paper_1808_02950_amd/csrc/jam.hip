@@ -158,7 +158,6 @@ struct JamArgs {
     double step_d;
     double skl[3][3];     // 1 / sqrt(n_k n_l) by (class of k, class of l)
     int32_t mu[3][3];     // sqrt(n_k n_l) where it is an integer, else 0
-    float inv2mu[3][3];   // 1 / (2 mu) (0 where irrational)
     int32_t cexact[3];    // L1 / n_k by class (exact inverse, no quantiser)
     double L;             // L1^2
     double inv_L;
@@ -166,21 +165,6 @@ struct JamArgs {
 };
 
 // ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ int rne_i32(double x) {
-    return __double2loint(x + 6755399441055744.0);   // 1.5 * 2^52
-}
-
-// round-half-away(y / (step mu)) in exact integer arithmetic: floor((2|y| + d) / 2d)
-__device__ __forceinline__ int quant_rational(int y, int d, float inv_2d) {
-    const int ay = y < 0 ? -y : y;
-    const int num = 2 * ay + d;
-    int q = int(float(num) * inv_2d);
-    const int rem = num - q * (2 * d);
-    q += (rem >= 2 * d) ? 1 : 0;
-    q -= (rem < 0) ? 1 : 0;
-    return y < 0 ? -q : q;
-}
 
 // round-half-to-even(n / L) clipped to [0, 255] for an integer n held exactly
 // in a double (|n| < 2^53).
@@ -619,7 +603,6 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
             for (int32_t s = 1; int64_t(s) * s <= v; ++s)
                 if (int64_t(s) * s == v) m = s;
             a.mu[i][k] = m;
-            a.inv2mu[i][k] = m ? float(0.5 / m) : 0.f;
             a.skl[i][k] = 1.0 / sqrt(double(v));
         }
     const int64_t L1 = int64_t(c) * 4 * 9 * 10 / 2;   // lcm(4c, 9c, 10c) = 180 c
