@@ -440,6 +440,25 @@ adct_status adct_filter_select(const uint64_t *sse_filtered, const uint64_t *sse
                                const adct_plane *planes, uint8_t *out, int64_t frame_stride_out, uint8_t *keep,
                                adct_stream_t stream);
 
+/* Checkpoint and resume of the post-filter (for callers that train, stop and
+ * continue, or ship trained weights): a self-checking host byte blob holding a
+ * 64-byte header (magic "ADCTFILT", format version 1, parameter count 9,857, a
+ * flag for the Adam moments, the Adam step, an FNV-1a 64-bit hash of the
+ * payload) and the float32 parameters, optionally followed by the moments m and
+ * v.  adct_filter_checkpoint_bytes(with_moments) is the blob size.
+ *   save: params (and m, v: both or neither, nullable) device float32 [9857];
+ *         blob host, blob_bytes at least the size (ADCT_ECAP); synchronises.
+ *   load: validates the whole blob on the host before any copy (ADCT_EINVAL for
+ *         a wrong magic, version, count or hash, or moments asked of a blob
+ *         without them; ADCT_EDIM for a size that does not match its header),
+ *         then fills params (and m, v when given) and *step (nullable);
+ *         synchronises. */
+int64_t adct_filter_checkpoint_bytes(int with_moments);
+adct_status adct_filter_save(const float *params, const float *m, const float *v, int step, void *blob,
+                             int64_t blob_bytes, adct_stream_t stream);
+adct_status adct_filter_load(const void *blob, int64_t blob_bytes, float *params, float *m, float *v, int *step,
+                             adct_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

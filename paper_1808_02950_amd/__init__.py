@@ -92,6 +92,9 @@ _SIGNATURES = {
                                     ctypes.c_float, _P, _P, _I, _I, _I, _P, _I64, _P, _P]),
     "adct_filter_apply": (_I, [_P, _P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _I64, _P, _I64, _P, _P]),
     "adct_filter_select": (_I, [_P, _P, _I, _I, _P, _I64, ctypes.POINTER(Plane), _P, _I64, _P, _P]),
+    "adct_filter_checkpoint_bytes": (_I64, [_I]),
+    "adct_filter_save": (_I, [_P, _P, _P, _I, _P, _I64, _P]),
+    "adct_filter_load": (_I, [_P, _I64, _P, _P, _P, ctypes.POINTER(_I), _P]),
 }
 
 
@@ -546,6 +549,31 @@ def filter_adam(params, m, v, grad, step: int, lr: float, beta1: float = 0.9, be
                                   _stream(stream)))
 
 
+def filter_save(params, m=None, v=None, step: int = 0, stream=None) -> bytes:
+    """adct_filter_save: a checkpoint blob of the float32 CUDA parameters (and the
+    Adam moments m, v with the step, when given)."""
+    import torch
+    _need_cuda(params, torch.float32, "params")
+    n = lib().adct_filter_checkpoint_bytes(1 if m is not None else 0)
+    buf = ctypes.create_string_buffer(n)
+    _check(lib().adct_filter_save(_ptr(params), _ptr(m), _ptr(v), step, ctypes.cast(buf, _P), n, _stream(stream)))
+    return buf.raw
+
+
+def filter_load(blob: bytes, params, m=None, v=None, stream=None) -> int:
+    """adct_filter_load into float32 CUDA tensors; returns the saved Adam step."""
+    import torch
+    _need_cuda(params, torch.float32, "params")
+    for name, t in (("params", params), ("m", m), ("v", v)):
+        if t is not None and (t.numel() != FILTER_PARAMS or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous tensor of {FILTER_PARAMS} floats")
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    step = _I()
+    _check(lib().adct_filter_load(ctypes.cast(buf, _P), len(blob), _ptr(params), _ptr(m), _ptr(v),
+                                  ctypes.byref(step), _stream(stream)))
+    return step.value
+
+
 class FilterTrainer:
     """Adam training of the post-filter on device batches through
     adct_filter_train_step.  params: float32 (9857,) numpy or CUDA tensor."""
@@ -581,24 +609,25 @@ class FilterTrainer:
         return filter_pack(self.params, stream=stream)
 
     def save(self, path: str):
-        """Checkpoint: float32 master weights, Adam moments, step count and
-        hyper-parameters in a numpy .npz file (plain arrays, no pickled objects)."""
-        np.savez(path, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
-                 step_count=np.int64(self.step_count), shape=np.array(self.shape, dtype=np.int64),
+        """Checkpoint: the library's self-checking blob (float32 master weights,
+        Adam moments, step; adct_filter_save) with the batch shape and the
+        hyper-parameters, in a numpy .npz file (plain arrays, no pickled objects)."""
+        blob = filter_save(self.params, self.m, self.v, self.step_count)
+        np.savez(path, blob=np.frombuffer(blob, dtype=np.uint8), shape=np.array(self.shape, dtype=np.int64),
                  hyper=np.array([self.lr, self.beta1, self.beta2, self.eps], dtype=np.float64))
 
     @classmethod
     def load(cls, path: str, device="cuda"):
         """Resume from a checkpoint written by save(); continuing gives the same
-        weights as an uninterrupted run (the gradient is deterministic)."""
-        import torch
+        weights as an uninterrupted run (the gradient is deterministic).  The
+        blob is validated (magic, version, size, hash) by adct_filter_load."""
         with np.load(path, allow_pickle=False) as z:
             n, h, w = (int(x) for x in z["shape"])
             lr, b1, b2, eps = (float(x) for x in z["hyper"])
-            tr = cls(z["params"], n, h, w, lr=lr, beta1=b1, beta2=b2, eps=eps, device=device)
-            tr.m.copy_(torch.from_numpy(z["m"]))
-            tr.v.copy_(torch.from_numpy(z["v"]))
-            tr.step_count = int(z["step_count"])
+            blob = z["blob"].tobytes()
+        tr = cls(np.zeros(FILTER_PARAMS, dtype=np.float32), n, h, w, lr=lr, beta1=b1, beta2=b2, eps=eps,
+                 device=device)
+        tr.step_count = filter_load(blob, tr.params, tr.m, tr.v)
         return tr
 
 

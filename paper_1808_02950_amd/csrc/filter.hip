@@ -31,6 +31,8 @@
 //    strip of 14 output columns x 32 rows.  Layer 1 is evaluated at the three
 //    column shifts layer 2 needs; layer 3 shifts its input one lane left and
 //    right with DPP.  No activation touches memory.
+#include <string.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -1292,6 +1294,95 @@ adct_status adct_filter_select(const uint64_t *sse_filtered, const uint64_t *sse
                        reinterpret_cast<const unsigned long long *>(sse_reference), plain, frame_stride_plain, out,
                        frame_stride_out, keep, a);
     ADCT_HIP(hipGetLastError());
+    return ADCT_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint
+//
+// Host blob: 64-byte header, then float32 params [kParams] and, when flag bit 0
+// is set, the Adam moments m and v [kParams] each.  Header: magic "ADCTFILT",
+// uint32 version (1), uint32 parameter count, uint32 flags, int32 Adam step,
+// uint64 FNV-1a hash of the payload bytes, zero padding.
+
+namespace {
+constexpr char kCkMagic[8] = {'A', 'D', 'C', 'T', 'F', 'I', 'L', 'T'};
+constexpr uint32_t kCkVersion = 1;
+struct CkHeader {
+    char magic[8];
+    uint32_t version, count, flags;
+    int32_t step;
+    uint64_t hash;
+    uint8_t pad[32];
+};
+static_assert(sizeof(CkHeader) == 64, "checkpoint header is 64 bytes");
+
+uint64_t fnv1a(const uint8_t *p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+}  // namespace
+
+int64_t adct_filter_checkpoint_bytes(int with_moments) {
+    return int64_t(sizeof(CkHeader)) + int64_t(with_moments ? 3 : 1) * kParams * int64_t(sizeof(float));
+}
+
+adct_status adct_filter_save(const float *params, const float *m, const float *v, int step, void *blob,
+                             int64_t blob_bytes, adct_stream_t stream) {
+    if (!params || !blob) return fail(ADCT_EINVAL, "params and blob are required");
+    if ((m == nullptr) != (v == nullptr)) return fail(ADCT_EINVAL, "m and v go together");
+    const int with = m != nullptr;
+    const int64_t need = adct_filter_checkpoint_bytes(with);
+    if (blob_bytes < need) return fail(ADCT_ECAP, "blob is smaller than adct_filter_checkpoint_bytes()");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *payload = static_cast<uint8_t *>(blob) + sizeof(CkHeader);
+    const size_t part = size_t(kParams) * sizeof(float);
+    ADCT_HIP(hipMemcpyAsync(payload, params, part, hipMemcpyDeviceToHost, s));
+    if (with) {
+        ADCT_HIP(hipMemcpyAsync(payload + part, m, part, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(payload + 2 * part, v, part, hipMemcpyDeviceToHost, s));
+    }
+    ADCT_HIP(hipStreamSynchronize(s));
+    CkHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kCkMagic, 8);
+    h.version = kCkVersion;
+    h.count = kParams;
+    h.flags = uint32_t(with);
+    h.step = step;
+    h.hash = fnv1a(payload, size_t(need) - sizeof(CkHeader));
+    memcpy(blob, &h, sizeof(h));
+    return ADCT_OK;
+}
+
+adct_status adct_filter_load(const void *blob, int64_t blob_bytes, float *params, float *m, float *v, int *step,
+                             adct_stream_t stream) {
+    if (!blob || !params) return fail(ADCT_EINVAL, "blob and params are required");
+    if ((m == nullptr) != (v == nullptr)) return fail(ADCT_EINVAL, "m and v go together");
+    if (blob_bytes < int64_t(sizeof(CkHeader))) return fail(ADCT_EDIM, "blob is shorter than its header");
+    CkHeader h;
+    memcpy(&h, blob, sizeof(h));
+    if (memcmp(h.magic, kCkMagic, 8) != 0) return fail(ADCT_EINVAL, "not a post-filter checkpoint");
+    if (h.version != kCkVersion || h.count != uint32_t(kParams) || h.flags > 1)
+        return fail(ADCT_EINVAL, "checkpoint version or parameter count does not match this library");
+    const int64_t need = adct_filter_checkpoint_bytes(int(h.flags));
+    if (blob_bytes != need) return fail(ADCT_EDIM, "blob size does not match its header");
+    const uint8_t *payload = static_cast<const uint8_t *>(blob) + sizeof(CkHeader);
+    if (fnv1a(payload, size_t(need) - sizeof(CkHeader)) != h.hash)
+        return fail(ADCT_EINVAL, "checkpoint payload is corrupted (hash mismatch)");
+    if (m && !h.flags) return fail(ADCT_EINVAL, "the checkpoint holds no optimiser moments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t part = size_t(kParams) * sizeof(float);
+    ADCT_HIP(hipMemcpyAsync(params, payload, part, hipMemcpyHostToDevice, s));
+    if (m) {
+        ADCT_HIP(hipMemcpyAsync(m, payload + part, part, hipMemcpyHostToDevice, s));
+        ADCT_HIP(hipMemcpyAsync(v, payload + 2 * part, part, hipMemcpyHostToDevice, s));
+    }
+    ADCT_HIP(hipStreamSynchronize(s));
+    if (step) *step = h.step;
     return ADCT_OK;
 }
 

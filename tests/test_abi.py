@@ -284,3 +284,37 @@ def test_coding_gain_argument_errors_host_only():
     assert lib.adct_coding_gain_sweep(None, 1, rho.ctypes.data, 1, out.ctypes.data, None) == -1
     assert lib.adct_coding_gain_sweep(c.ctypes.data, 0, rho.ctypes.data, 1, out.ctypes.data, None) == -3
     assert lib.adct_coding_gain_sweep(c.ctypes.data, 1, rho.ctypes.data, 2, out.ctypes.data, None) == -3
+
+
+def test_filter_checkpoint_validation_host_only():
+    """adct_filter_load checks the whole blob on the host before any copy."""
+    import struct
+    lib = A.lib()
+    n1, n3 = lib.adct_filter_checkpoint_bytes(0), lib.adct_filter_checkpoint_bytes(1)
+    assert n1 == 64 + 9857 * 4 and n3 == 64 + 3 * 9857 * 4
+    FAKE = ctypes.c_void_p(4096)
+
+    def blob(magic=b"ADCTFILT", version=1, count=9857, flags=0, payload=None, size=None):
+        payload = bytes(9857 * 4 * (3 if flags else 1)) if payload is None else payload
+        h = 1469598103934665603
+        for byte in payload:                                   # FNV-1a 64
+            h = ((h ^ byte) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+        head = magic + struct.pack("<IIIiQ", version, count, flags, 7, h) + bytes(32)
+        b = head + payload
+        return b if size is None else b[:size]
+
+    def load(b, m=None):
+        buf = ctypes.create_string_buffer(b, len(b))
+        return lib.adct_filter_load(ctypes.cast(buf, ctypes.c_void_p), len(b), FAKE, m, m, None, None)
+    assert load(blob(magic=b"NOTAFILT")) == -1
+    assert load(blob(version=2)) == -1
+    assert load(blob(count=100)) == -1
+    assert load(blob(size=n1 - 4)) == -2
+    assert load(blob()[:32]) == -2
+    good = bytearray(blob())
+    good[100] ^= 1                                             # corrupt one payload byte
+    assert load(bytes(good)) == -1
+    assert load(blob(), m=FAKE) == -1                          # moments asked, none stored
+    assert lib.adct_filter_save(None, None, None, 0, FAKE, n1, None) == -1
+    assert lib.adct_filter_save(FAKE, FAKE, None, 0, FAKE, n3, None) == -1
+    assert lib.adct_filter_save(FAKE, None, None, 0, FAKE, n1 - 1, None) == -5

@@ -403,3 +403,25 @@ def test_checkpoint_resume_is_exact(cuda, tmp_path):
     for a, b in ((full.params, resumed.params), (full.m, resumed.m), (full.v, resumed.v)):
         assert torch.equal(a, b)
     assert not torch.equal(full.params, torch.from_numpy(p0).to(cuda))
+
+
+def test_checkpoint_blob_roundtrip(cuda):
+    """adct_filter_save / adct_filter_load: parameters, moments and step come
+    back bit for bit; a corrupted blob is refused before anything is copied."""
+    import torch
+    p = torch.from_numpy(filter_params(5)).to(cuda)
+    m = torch.randn(A.FILTER_PARAMS, device=cuda)
+    v = torch.rand(A.FILTER_PARAMS, device=cuda)
+    blob = A.filter_save(p, m, v, step=123)
+    p2, m2, v2 = torch.zeros_like(p), torch.zeros_like(m), torch.zeros_like(v)
+    assert A.filter_load(blob, p2, m2, v2) == 123
+    assert torch.equal(p, p2) and torch.equal(m, m2) and torch.equal(v, v2)
+    only = A.filter_save(p)
+    p3 = torch.zeros_like(p)
+    assert A.filter_load(only, p3) == 0 and torch.equal(p, p3)
+    bad = bytearray(blob)
+    bad[-1] ^= 0x40
+    p4 = torch.full_like(p, 7.0)
+    with pytest.raises(A.AdctError):
+        A.filter_load(bytes(bad), p4)
+    assert bool((p4 == 7.0).all())
