@@ -34,7 +34,6 @@ namespace {
 
 constexpr double kTieEps = 1e-12;     // cosines this close are an exact tie in reals
 constexpr double kWindow = 1e-6;      // collection window below the best cosine
-constexpr int kMaxChosen = 7;
 constexpr int kHistBins = 448;        // 8 bins per octave of 1 - cos, 56 octaves
 
 struct DctRows {
@@ -117,36 +116,30 @@ __global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, uint8_t *prim) {
 
 // ------------------------------------------------------------ greedy queries
 
+// A query: DCT row `row` against the candidates of one feasible list (the
+// candidates orthogonal to every row chosen so far, as space indices).
 struct Query {
-    uint2 chosen[kMaxChosen];
-    int nchosen;
-    int row;
+    int64_t off;          // first entry of the list in the level's list arena
+    int32_t len;
+    int32_t row;
 };
 
-__device__ __forceinline__ bool feasible(const Query &q, uint2 v) {
-    bool ok = true;
-    for (int j = 0; j < q.nchosen; ++j) ok &= sdot8(v, q.chosen[j]) == 0;
-    return ok;
-}
-
-__global__ __launch_bounds__(256) void k_qmax(const Query *qs, int64_t n, const uint2 *vec,
+__global__ __launch_bounds__(256) void k_qmax(const Query *qs, const uint32_t *lists, const uint2 *vec,
                                              const DctRows rows, unsigned long long *best) {
     const Query q = qs[blockIdx.y];
     double m = -2.0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const uint2 p = vec[i];
-        if (feasible(q, p)) {
-            int v[8];
-            unpack8(p, v);
-            m = fmax(m, cos_row(v, inv_norm(p), rows, q.row));
-        }
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < q.len;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const uint2 p = vec[lists[q.off + t]];
+        int v[8];
+        unpack8(p, v);
+        m = fmax(m, cos_row(v, inv_norm(p), rows, q.row));
     }
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0 && m > -2.0) atomicMax(best + blockIdx.y, order_key(m));
 }
 
-__global__ __launch_bounds__(256) void k_qcollect(const Query *qs, int64_t n, const uint2 *vec,
+__global__ __launch_bounds__(256) void k_qcollect(const Query *qs, const uint32_t *lists, const uint2 *vec,
                                                  const DctRows rows, const unsigned long long *best,
                                                  int cap, int64_t *out_idx, double *out_cos,
                                                  int *count) {
@@ -154,20 +147,54 @@ __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, int64_t n, co
     if (best[qi] == 0) return;                                  // no feasible candidate
     const Query q = qs[qi];
     const double lo = key_value(best[qi]) - kWindow;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < q.len;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t i = lists[q.off + t];
         const uint2 p = vec[i];
-        if (!feasible(q, p)) continue;
         int v[8];
         unpack8(p, v);
         const double c = cos_row(v, inv_norm(p), rows, q.row);
         if (c >= lo) {
             const int pos = atomicAdd(count + qi, 1);
             if (pos < cap) {
-                out_idx[int64_t(qi) * cap + pos] = i;
+                out_idx[int64_t(qi) * cap + pos] = int64_t(i);
                 out_cos[int64_t(qi) * cap + pos] = c;
             }
         }
+    }
+}
+
+// Feasible lists.  The root list holds every candidate orthogonal to the fixed
+// rows; a child state's list keeps the parent's entries orthogonal to the
+// candidate just chosen (the chosen one itself drops out: |v|^2 > 0).  Entry
+// order inside a list follows the atomics and does not matter: the queries take
+// a maximum and a window, and the host orders what they collect.
+__global__ __launch_bounds__(256) void k_root_list(int64_t n, const uint2 *vec, uint2 f0, uint2 f1, int nfixed,
+                                                  uint32_t *out, int *len) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const uint2 p = vec[i];
+        bool ok = true;
+        if (nfixed > 0) ok &= sdot8(p, f0) == 0;
+        if (nfixed > 1) ok &= sdot8(p, f1) == 0;
+        if (ok) out[atomicAdd(len, 1)] = uint32_t(i);
+    }
+}
+
+struct FilterJob {
+    int64_t in_off, out_off;
+    int32_t in_len;
+    uint32_t chosen;      // space index of the candidate just chosen
+};
+
+__global__ __launch_bounds__(256) void k_filter(const uint2 *vec, const uint32_t *in, const FilterJob *jobs,
+                                               uint32_t *out, int *lens) {
+    const FilterJob j = jobs[blockIdx.y];
+    const uint2 c = vec[j.chosen];
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < j.in_len;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t i = in[j.in_off + t];
+        if (sdot8(vec[i], c) == 0) out[j.out_off + atomicAdd(lens + blockIdx.y, 1)] = i;
     }
 }
 
@@ -429,6 +456,9 @@ struct State {
     int node;
     int8_t rows[8][8];
     bool set[8];
+    int64_t loff;         // the state's feasible list in the current level's arena
+    int32_t llen;
+    uint32_t chosen;      // space index of the candidate chosen last (for the child list)
 };
 
 struct MatKey {
@@ -438,7 +468,7 @@ struct MatKey {
 
 // Answer a batch of queries: per query the collected window (or none when the
 // feasible set is empty).
-adct_status run_queries(const Space &sp, const std::vector<Query> &qs,
+adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vector<Query> &qs,
                         std::vector<std::vector<Cand>> &res, std::vector<char> &dead, hipStream_t s) {
     const int nq = int(qs.size());
     res.assign(nq, {});
@@ -452,10 +482,12 @@ adct_status run_queries(const Space &sp, const std::vector<Query> &qs,
     if ((st = dalloc<int>(dcount, nq))) return st;
     ADCT_HIP(hipMemcpyAsync(dq.p, qs.data(), sizeof(Query) * nq, hipMemcpyHostToDevice, s));
     ADCT_HIP(hipMemsetAsync(dbest.p, 0, sizeof(unsigned long long) * nq, s));
-    const unsigned chunks = unsigned(std::min<int64_t>((sp.n + 255) / 256, 64));
+    int64_t maxlen = 1;
+    for (const Query &q : qs) maxlen = std::max<int64_t>(maxlen, q.len);
+    const unsigned chunks = unsigned(std::min<int64_t>((maxlen + 255) / 256, 64));
     for (int y0 = 0; y0 < nq; y0 += 65535) {
         const int ny = std::min(nq - y0, 65535);
-        hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, sp.n,
+        hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, lists,
                            (const uint2 *)sp.vec.p, dct_rows(), (unsigned long long *)dbest.p + y0);
         ADCT_HIP(hipGetLastError());
     }
@@ -467,7 +499,7 @@ adct_status run_queries(const Space &sp, const std::vector<Query> &qs,
         for (int y0 = 0; y0 < nq; y0 += 65535) {
             const int ny = std::min(nq - y0, 65535);
             hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0,
-                               sp.n, (const uint2 *)sp.vec.p, dct_rows(),
+                               lists, (const uint2 *)sp.vec.p, dct_rows(),
                                (const unsigned long long *)dbest.p + y0, cap,
                                (int64_t *)didx.p + int64_t(y0) * cap, (double *)dcos.p + int64_t(y0) * cap,
                                (int *)dcount.p + y0);
@@ -590,13 +622,27 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
     State root;
     memset(&root, 0, sizeof(root));
     root.node = 0;
+    const int8_t r0[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    const int8_t r4[8] = {1, -1, -1, 1, 1, -1, -1, 1};
     if (fix_rows_1_5) {
-        const int8_t r0[8] = {1, 1, 1, 1, 1, 1, 1, 1};
-        const int8_t r4[8] = {1, -1, -1, 1, 1, -1, -1, 1};
         memcpy(root.rows[0], r0, 8);
         memcpy(root.rows[4], r4, 8);
         root.set[0] = root.set[4] = true;
     }
+    // the root's feasible list: every candidate orthogonal to the fixed rows
+    DevBuf lists, dlen;
+    if ((st = dalloc<uint32_t>(lists, sp.n))) return st;
+    if ((st = dalloc<int>(dlen, 1))) return st;
+    ADCT_HIP(hipMemsetAsync(dlen.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_root_list, dim3(unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048))), dim3(256), 0, s,
+                       sp.n, (const uint2 *)sp.vec.p, pack8(r0), pack8(r4), fix_rows_1_5 ? 2 : 0,
+                       (uint32_t *)lists.p, (int *)dlen.p);
+    ADCT_HIP(hipGetLastError());
+    int root_len = 0;
+    ADCT_HIP(hipMemcpyAsync(&root_len, dlen.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipStreamSynchronize(s));
+    root.loff = 0;
+    root.llen = root_len;
     std::map<MatKey, adct_matrix> found;
     int64_t leaves = 0, dead = 0;
     std::vector<State> frontier{root};
@@ -607,9 +653,8 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
             const State &S = frontier[si];
             for (const auto &kv : tr.kids[S.node]) {
                 Query q;
-                memset(&q, 0, sizeof(q));
-                for (int k = 0; k < 8; ++k)
-                    if (S.set[k]) q.chosen[q.nchosen++] = pack8(S.rows[k]);
+                q.off = S.loff;
+                q.len = S.llen;
                 q.row = kv.first;
                 qs.push_back(q);
                 qmeta.emplace_back(int(si), kv.first);
@@ -617,7 +662,7 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
         }
         std::vector<std::vector<Cand>> res;
         std::vector<char> isdead;
-        if ((st = run_queries(sp, qs, res, isdead, s))) return st;
+        if ((st = run_queries(sp, (const uint32_t *)lists.p, qs, res, isdead, s))) return st;
         std::vector<State> next;
         for (size_t q = 0; q < qs.size(); ++q) {
             const State &S = frontier[qmeta[q].first];
@@ -637,6 +682,7 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
                 N.node = child;
                 decode_index(sp, c.idx, N.rows[row]);
                 N.set[row] = true;
+                N.chosen = uint32_t(c.idx - 1);
                 if (tr.kids[child].empty()) {
                     adct_matrix m;
                     fill_matrix(N.rows, &m);
@@ -648,6 +694,43 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
                     next.push_back(N);
                 }
             }
+        }
+        // the next level's feasible lists: each child filters its parent's list
+        if (!next.empty()) {
+            std::vector<FilterJob> jobs(next.size());
+            int64_t total = 0;
+            for (size_t j = 0; j < next.size(); ++j) {
+                jobs[j].in_off = next[j].loff;
+                jobs[j].in_len = next[j].llen;
+                jobs[j].out_off = total;
+                jobs[j].chosen = next[j].chosen;
+                total += next[j].llen;
+            }
+            const int nj = int(next.size());
+            DevBuf nl, dj, dl;
+            if ((st = dalloc<uint32_t>(nl, std::max<int64_t>(total, 1)))) return st;
+            if ((st = dalloc<FilterJob>(dj, nj))) return st;
+            if ((st = dalloc<int>(dl, nj))) return st;
+            ADCT_HIP(hipMemcpyAsync(dj.p, jobs.data(), sizeof(FilterJob) * nj, hipMemcpyHostToDevice, s));
+            ADCT_HIP(hipMemsetAsync(dl.p, 0, sizeof(int) * nj, s));
+            int64_t maxlen = 1;
+            for (const FilterJob &j : jobs) maxlen = std::max<int64_t>(maxlen, j.in_len);
+            const unsigned chunks = unsigned(std::min<int64_t>((maxlen + 255) / 256, 64));
+            for (int y0 = 0; y0 < nj; y0 += 65535) {
+                const int ny = std::min(nj - y0, 65535);
+                hipLaunchKernelGGL(k_filter, dim3(chunks, ny), dim3(256), 0, s, (const uint2 *)sp.vec.p,
+                                   (const uint32_t *)lists.p, (const FilterJob *)dj.p + y0, (uint32_t *)nl.p,
+                                   (int *)dl.p + y0);
+                ADCT_HIP(hipGetLastError());
+            }
+            std::vector<int> lens(nj);
+            ADCT_HIP(hipMemcpyAsync(lens.data(), dl.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
+            ADCT_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < nj; ++j) {
+                next[j].loff = jobs[j].out_off;
+                next[j].llen = lens[j];
+            }
+            std::swap(lists.p, nl.p);     // the parent arena is freed with nl
         }
         frontier.swap(next);
     }
