@@ -58,7 +58,12 @@ __device__ __forceinline__ int rne_div_exact(double n, double den, double inv_de
     return qi + ((twice > den || (twice == den && (qi & 1))) ? 1 : 0);
 }
 
+// BAND: only coefficients (k, l) with k + l <= BAND can be kept (r <= 10 needs
+// BAND 3; 14 is the whole block); the products that only reach discarded
+// coefficients or columns drop out at compile time.
+template <int BAND>
 __global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
+    constexpr int KB = BAND + 1 < 8 ? BAND + 1 : 8;     // columns (and rows) that can hold kept coefficients
     const int lane = threadIdx.x & 63;
     const int total = a.n_frames * a.waves_per_frame;
     unsigned long long acc = 0;
@@ -83,25 +88,27 @@ __global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
             pix[x][1] = v.y;
         }
         // Y = T A T^T, then the zig-zag prefix
-        int Z[8][8];
+        int Z[8][KB];
 #pragma unroll
         for (int x = 0; x < 8; ++x)
 #pragma unroll
-            for (int l = 0; l < 8; ++l) {
+            for (int l = 0; l < KB; ++l) {
                 int s = 0;
 #pragma unroll
                 for (int m = 0; m < 8; ++m) s += a.T[8 * l + m] * int((pix[x][m >> 2] >> (8 * (m & 3))) & 0xffu);
                 Z[x][l] = s;
             }
-        int Y[8][8];
+        int Y[KB][KB];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < KB; ++k)
 #pragma unroll
-            for (int l = 0; l < 8; ++l) {
+            for (int l = 0; l < KB; ++l) {
                 int s = 0;
+                if (k + l <= BAND) {
 #pragma unroll
-                for (int x = 0; x < 8; ++x) s += a.T[8 * k + x] * Z[x][l];
-                Y[k][l] = (zz_pos(k, l) < a.r) ? s : 0;
+                    for (int x = 0; x < 8; ++x) s += a.T[8 * k + x] * Z[x][l];
+                }
+                Y[k][l] = (k + l <= BAND && zz_pos(k, l) < a.r) ? s : 0;
             }
         // numerator adj Y' adj^T row by row (integers, exact in float64); the
         // row loop stays rolled (one row's sums live at a time) and re-reads the
@@ -111,12 +118,13 @@ __global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
 #pragma unroll 1
         for (int x = 0; x < 8; ++x) {
             const u32x2 px = *(const u32x2 *)(src + int64_t(x) * P.pitch);
-            double U[8];
+            double U[KB];
 #pragma unroll
-            for (int l = 0; l < 8; ++l) {
+            for (int l = 0; l < KB; ++l) {
                 double s = 0.0;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) s = fma(a.adj[8 * x + k], double(Y[k][l]), s);
+                for (int k = 0; k < KB; ++k)
+                    if (k + l <= BAND) s = fma(a.adj[8 * x + k], double(Y[k][l]), s);
                 U[l] = s;
             }
             uint32_t lo = 0, hi = 0;
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
             for (int y = 0; y < 8; ++y) {
                 double s = 0.0;
 #pragma unroll
-                for (int l = 0; l < 8; ++l) s = fma(U[l], a.adj[8 * y + l], s);
+                for (int l = 0; l < KB; ++l) s = fma(U[l], a.adj[8 * y + l], s);
                 const int q = rne_div_exact(s, a.den, a.inv_den);
                 const int d = q - int(((y < 4 ? px.x : px.y) >> (8 * (y & 3))) & 0xffu);
                 e += unsigned(d * d);
@@ -323,10 +331,12 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     int dev = 0, cus = 0, per_cu = 0;
     ADCT_HIP(hipGetDevice(&dev));
     ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_inverse_codec, 256, 0));
+    // r <= 10 keeps only coefficients with k + l <= 3
+    auto kern = r <= 10 ? k_inverse_codec<3> : k_inverse_codec<14>;
+    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
     const int64_t want = (waves * n_frames + 3) / 4;
     const int grid = int(std::min<int64_t>(want, int64_t(std::max(per_cu, 1)) * cus));
-    hipLaunchKernelGGL(k_inverse_codec, dim3(grid), dim3(256), 0, hs, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, hs, a);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }
