@@ -558,6 +558,8 @@ def main():
         "config": {"workload": f"video stream {spec.n_frames} frames 3840x2160 YUV 4:2:0 uint8",
                    "transform": "T1", "r": r, "quant_step": step, "schedule": args.schedule,
                    "samples_per_frame": spec.frame_bytes, "blocks_per_launch": blocks},
+        "frames_per_s": round(spec.n_frames / (ms_per_step / 1e3), 1),
+        "luma_Mpixel_per_s": round(spec.n_frames * spec.width * spec.height / (ms_per_step / 1e3) / 1e6, 1),
         "psnr_db": {"T1_frame_mean": round(psnr_frame, 4),
                     "T1_Y": round(psnr_planes[0], 4), "T1_U": round(psnr_planes[1], 4),
                     "T1_V": round(psnr_planes[2], 4),
