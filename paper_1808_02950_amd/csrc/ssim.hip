@@ -111,22 +111,22 @@ __device__ __forceinline__ void ssim_row(const SsimArgs &a, const uint8_t *rb, c
         h[3] = fma(wb, double(y[b] * y[b] + y[c] * y[c]), h[3]);
         h[4] = fma(wb, double(x[b] * y[b] + x[c] * y[c]), h[4]);
     }
-    // this row feeds output rows o = i - d, d = 0..10, of slot (U - d) mod 11
+    // this row feeds output rows o = i - d, d = 0..10, of slot (U - d) mod 11 =
+    // o mod 11; it is the first row of output o = i (d = 0), which starts the
+    // slot afresh, so a completed slot needs no clearing
 #pragma unroll
     for (int d = 0; d < kWin; ++d) {
         if (d <= i && i - d < nout) {
             double(&s)[5] = acc[(U - d + kWin) % kWin];
             const double wd = a.w[d];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) s[q] = fma(wd, h[q], s[q]);
+            for (int q = 0; q < 5; ++q) s[q] = d == 0 ? wd * h[q] : fma(wd, h[q], s[q]);
         }
     }
     // output row o = i - 10 is complete
     if (i >= kWin - 1 && i - (kWin - 1) < nout) {
-        double(&s)[5] = acc[(U + 1) % kWin];
+        const double(&s)[5] = acc[(U + 1) % kWin];
         if (col_ok) sum += ssim_at(s);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) s[q] = 0.0;
     }
 }
 

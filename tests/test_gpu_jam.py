@@ -156,3 +156,16 @@ def test_jam_exact_quantiser_ties(cuda, n):
         want = jam.evaluate(img, TN[n], r, step)
         assert np.array_equal(coef, want["coef_int"]), (r, step)
         assert np.array_equal(rec, want["rec"]) and sse == want["sse"], (r, step)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_jam_degenerate_shapes_and_largest_step(cuda, n):
+    """One-pixel, one-row and one-column planes (every block is edge-extended)
+    and the largest quantiser step the library takes (4096: nearly every level 0)."""
+    for shape in ((1, 1), (1, 700), (700, 1), (n + 1, n - 1)):
+        img = ar1_image(*shape, rho=0.9, seed=shape[0] + 3 * shape[1])
+        for r, step in ((1, 0), (7, n), (n * n, 4096)):
+            rec, sse, coef = _run_image(img, n, r, step, cuda)
+            want = jam.evaluate(img, TN[n], r, step)
+            assert np.array_equal(coef, want["coef_int"]), (shape, r, step)
+            assert np.array_equal(rec, want["rec"]) and sse == want["sse"], (shape, r, step)
