@@ -299,6 +299,8 @@ typedef enum { ADCT_SEARCH_CLOSURE = 0, ADCT_SEARCH_CANONICAL = 1 } adct_search_
  *                 the matching DCT row
  *   leaves_out, dead_out  host, nullable: completed and dead (order, tie
  *                 branch) paths
+ * Each search state keeps its feasible list (space indices, 4 bytes each) on the
+ * device for one depth; ADCT_ERANGE if a depth's lists would pass 32 GB.
  * Synchronises `stream`; allocates and frees its own device scratch. */
 adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8_t *orders,
                                   int n_orders, int fix_rows_1_5, adct_matrix *out, int cap_out,

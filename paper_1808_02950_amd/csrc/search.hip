@@ -707,6 +707,9 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
                 total += next[j].llen;
             }
             const int nj = int(next.size());
+            if (total > (int64_t(1) << 33))
+                return fail(ADCT_ERANGE, "the next depth's feasible lists would exceed 32 GB (fix rows 1 and 5, "
+                                         "or search fewer orders)");
             DevBuf nl, dj, dl;
             if ((st = dalloc<uint32_t>(nl, std::max<int64_t>(total, 1)))) return st;
             if ((st = dalloc<FilterJob>(dj, nj))) return st;
