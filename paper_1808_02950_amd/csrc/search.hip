@@ -40,8 +40,12 @@ struct DctRows {
     double c[64];                     // orthonormal DCT-II rows, c[8k + n]
 };
 
+// The digit values in canonical order, 5 bits each (value + 16), and the
+// reciprocal for dividing canonical indices by the base: for idx < 2^28 and a
+// base b <= 9, umulhi(idx, ceil(2^32 / b)) is the exact quotient.
 struct Digits {
-    int8_t d[12];
+    unsigned long long packed;
+    uint32_t magic;
 };
 
 DctRows dct_rows() {
@@ -66,7 +70,16 @@ __device__ __forceinline__ void unpack8(uint2 p, int (&v)[8]) {
 }
 
 // 1 / |v| in float64 (|v|^2 is an exact integer)
-__device__ __forceinline__ double inv_norm(uint2 p) { return 1.0 / sqrt(double(sdot8(p, p))); }
+// (|v|^2 is an exact integer, at most 8 * 64: a table of 1 / sqrt(n) for every
+// n replaces the square root and division in the scans; k_inv_table fills it
+// with the same float64 expression)
+constexpr int kMaxNorm2 = 512;
+__device__ __forceinline__ double inv_norm(uint2 p, const double *invt) { return invt[sdot8(p, p)]; }
+
+__global__ void k_inv_table(double *t) {
+    const int n = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (n <= kMaxNorm2) t[n] = n ? 1.0 / sqrt(double(n)) : 0.0;
+}
 
 // cos of the angle between v and DCT row r: the float64 dot product in entry
 // order, times 1 / |v| (the DCT rows have unit norm)
@@ -92,11 +105,14 @@ __host__ __device__ __forceinline__ double key_value(unsigned long long k) {
 __global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, uint8_t *prim) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int64_t idx = i + 1;                             // canonical index; 0 is the zero vector
+    uint32_t idx = uint32_t(i + 1);                  // canonical index; 0 is the zero vector
     int v[8];
+#pragma unroll
     for (int e = 7; e >= 0; --e) {                   // first coordinate most significant
-        v[e] = dg.d[idx % b];
-        idx /= b;
+        const uint32_t q = __umulhi(idx, dg.magic);
+        const uint32_t d = idx - q * uint32_t(b);
+        v[e] = int((dg.packed >> (5 * d)) & 31u) - 16;
+        idx = q;
     }
     uint32_t lo = 0, hi = 0;
     bool odd = false, non3 = false, non5 = false, non7 = false;
@@ -125,7 +141,7 @@ struct Query {
 };
 
 __global__ __launch_bounds__(256) void k_qmax(const Query *qs, const uint32_t *lists, const uint2 *vec,
-                                             const DctRows rows, unsigned long long *best) {
+                                             const double *invt, const DctRows rows, unsigned long long *best) {
     const Query q = qs[blockIdx.y];
     double m = -2.0;
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < q.len;
@@ -133,14 +149,15 @@ __global__ __launch_bounds__(256) void k_qmax(const Query *qs, const uint32_t *l
         const uint2 p = vec[lists[q.off + t]];
         int v[8];
         unpack8(p, v);
-        m = fmax(m, cos_row(v, inv_norm(p), rows, q.row));
+        m = fmax(m, cos_row(v, inv_norm(p, invt), rows, q.row));
     }
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0 && m > -2.0) atomicMax(best + blockIdx.y, order_key(m));
 }
 
 __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, const uint32_t *lists, const uint2 *vec,
-                                                 const DctRows rows, const unsigned long long *best,
+                                                 const double *invt, const DctRows rows,
+                                                 const unsigned long long *best,
                                                  int cap, int64_t *out_idx, double *out_cos,
                                                  int *count) {
     const int qi = blockIdx.y;
@@ -153,7 +170,7 @@ __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, const uint32_
         const uint2 p = vec[i];
         int v[8];
         unpack8(p, v);
-        const double c = cos_row(v, inv_norm(p), rows, q.row);
+        const double c = cos_row(v, inv_norm(p, invt), rows, q.row);
         if (c >= lo) {
             const int pos = atomicAdd(count + qi, 1);
             if (pos < cap) {
@@ -244,7 +261,7 @@ __device__ __forceinline__ int angle_bin(double c) {
 }
 
 __global__ __launch_bounds__(256) void k_hist(int64_t n, const uint2 *vec, const uint8_t *prim, int primitive,
-                                             const DctRows rows, unsigned *hist) {
+                                             const double *invt, const DctRows rows, unsigned *hist) {
     __shared__ unsigned h[8 * kHistBins];
     for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
@@ -254,7 +271,7 @@ __global__ __launch_bounds__(256) void k_hist(int64_t n, const uint2 *vec, const
         const uint2 p = vec[i];
         int v[8];
         unpack8(p, v);
-        const double inv = inv_norm(p);
+        const double inv = inv_norm(p, invt);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int bn = angle_bin(cos_row(v, inv, rows, r));
@@ -273,7 +290,8 @@ struct Thresholds {
 };
 
 __global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const uint2 *vec, const uint8_t *prim,
-                                                     int primitive, const DctRows rows, Thresholds th,
+                                                     int primitive, const double *invt, const DctRows rows,
+                                                     Thresholds th,
                                                      int64_t *out_idx, double *out_cos,
                                                      unsigned long long *count) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -282,7 +300,7 @@ __global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const uint2 *ve
         const uint2 p = vec[i];
         int v[8];
         unpack8(p, v);
-        const double inv = inv_norm(p);
+        const double inv = inv_norm(p, invt);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const double c = cos_row(v, inv, rows, r);
@@ -340,7 +358,7 @@ struct Space {
     int b = 0;
     int8_t digits[9] = {};
     int64_t n = 0;
-    DevBuf vec, prim;
+    DevBuf vec, prim, inv;
 };
 
 adct_status canonical_digits(const int8_t *P, int nP, int8_t *out, int *b) {
@@ -372,11 +390,16 @@ adct_status build_space(const int8_t *P, int nP, Space &sp, hipStream_t s) {
     if ((st = dalloc<uint2>(sp.vec, sp.n))) return st;
     if ((st = dalloc<uint8_t>(sp.prim, sp.n))) return st;
     Digits dg;
-    memset(&dg, 0, sizeof(dg));
-    for (int i = 0; i < sp.b; ++i) dg.d[i] = sp.digits[i];
+    dg.packed = 0;
+    for (int i = 0; i < sp.b; ++i) dg.packed |= (unsigned long long)(sp.digits[i] + 16) << (5 * i);
+    dg.magic = uint32_t(((uint64_t(1) << 32) + uint64_t(sp.b) - 1) / uint64_t(sp.b));   // ceil(2^32 / b)
+    if (sp.b == 1) dg.magic = 0xffffffffu;           // b = 1 never divides (only the zero vector)
     const int64_t blocks = (sp.n + 255) / 256;
     hipLaunchKernelGGL(k_enum, dim3(unsigned(blocks)), dim3(256), 0, s, sp.b, dg, sp.n,
                        (uint2 *)sp.vec.p, (uint8_t *)sp.prim.p);
+    ADCT_HIP(hipGetLastError());
+    if ((st = dalloc<double>(sp.inv, kMaxNorm2 + 1))) return st;
+    hipLaunchKernelGGL(k_inv_table, dim3((kMaxNorm2 + 256) / 256), dim3(256), 0, s, (double *)sp.inv.p);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }
@@ -488,7 +511,8 @@ adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vecto
     for (int y0 = 0; y0 < nq; y0 += 65535) {
         const int ny = std::min(nq - y0, 65535);
         hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, lists,
-                           (const uint2 *)sp.vec.p, dct_rows(), (unsigned long long *)dbest.p + y0);
+                           (const uint2 *)sp.vec.p, (const double *)sp.inv.p, dct_rows(),
+                           (unsigned long long *)dbest.p + y0);
         ADCT_HIP(hipGetLastError());
     }
     for (;;) {
@@ -499,7 +523,7 @@ adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vecto
         for (int y0 = 0; y0 < nq; y0 += 65535) {
             const int ny = std::min(nq - y0, 65535);
             hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0,
-                               lists, (const uint2 *)sp.vec.p, dct_rows(),
+                               lists, (const uint2 *)sp.vec.p, (const double *)sp.inv.p, dct_rows(),
                                (const unsigned long long *)dbest.p + y0, cap,
                                (int64_t *)didx.p + int64_t(y0) * cap, (double *)dcos.p + int64_t(y0) * cap,
                                (int *)dcount.p + y0);
@@ -764,7 +788,8 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     ADCT_HIP(hipMemsetAsync(dhist.p, 0, sizeof(unsigned) * 8 * kHistBins, s));
     const unsigned grid = unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048));
     hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec.p,
-                       (const uint8_t *)sp.prim.p, primitive, dct_rows(), (unsigned *)dhist.p);
+                       (const uint8_t *)sp.prim.p, primitive, (const double *)sp.inv.p, dct_rows(),
+                       (unsigned *)dhist.p);
     ADCT_HIP(hipGetLastError());
     std::vector<unsigned> hist(8 * kHistBins);
     ADCT_HIP(hipMemcpyAsync(hist.data(), dhist.p, sizeof(unsigned) * hist.size(), hipMemcpyDeviceToHost, s));
@@ -792,7 +817,8 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     if ((st = dalloc<unsigned long long>(dcnt, 8))) return st;
     ADCT_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(unsigned long long) * 8, s));
     hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec.p,
-                       (const uint8_t *)sp.prim.p, primitive, dct_rows(), th, (int64_t *)didx.p,
+                       (const uint8_t *)sp.prim.p, primitive, (const double *)sp.inv.p, dct_rows(), th,
+                       (int64_t *)didx.p,
                        (double *)dcos.p, (unsigned long long *)dcnt.p);
     ADCT_HIP(hipGetLastError());
     std::vector<int64_t> idx(std::max<int64_t>(total, 1));
