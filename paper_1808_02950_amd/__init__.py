@@ -140,6 +140,18 @@ def _need_cuda(t, dtype, name):
         raise TypeError(f"{name} must be {dtype}")
 
 
+def _check_frames(name, buf, planes, nf):
+    """Every byte a kernel reads or writes through `planes` must lie inside the
+    (n_frames, frame_bytes) tensor `buf` (None passes)."""
+    if buf is None:
+        return
+    if buf.dim() != 2 or buf.stride(1) != 1 or buf.shape[0] != nf:
+        raise ValueError(f"{name} must be (n_frames, frame_bytes) with unit inner stride")
+    for off, h, w, pitch in planes:
+        if off < 0 or h < 1 or w < 1 or off + (h - 1) * pitch + w > buf.shape[1]:
+            raise ValueError(f"a plane reaches outside a frame of {name}")
+
+
 # ---------------------------------------------------------------- host-only
 
 def version() -> int:
@@ -250,8 +262,16 @@ def evaluate_stream(frames, planes, t, r: int, quant_step: int = 0, coef=None, r
     import torch
     _need_cuda(frames, torch.uint8, "frames")
     nf = frames.shape[0]
+    _check_frames("frames", frames, planes, nf)
+    if recon is not None:
+        _need_cuda(recon, torch.uint8, "recon")
+        _check_frames("recon", recon, planes, nf)
+    if coef is not None and coef.numel() < nf * stream_blocks_per_frame(planes) * r:
+        raise ValueError("coef needs n_frames * blocks * r entries")
     if sse is None:
         sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
+    elif sse.numel() < nf * len(planes):
+        raise ValueError("sse is too small")
     arr = planes_struct(planes)
     _check(lib().adct_evaluate_stream(_ptr(frames), frames.stride(0), nf, arr, len(planes), _tid(t),
                                       None, r, quant_step, _ptr(coef), _ptr(recon),
@@ -276,6 +296,8 @@ def ssim(ref, test, planes, out=None, stream=None):
         nf, fs_r, fs_t = 1, 0, 0
     else:
         nf, fs_r, fs_t = ref.shape[0], ref.stride(0), test.stride(0)
+        _check_frames("ref", ref, planes, nf)
+        _check_frames("test", test, planes, nf)
     if test.shape[0] != ref.shape[0]:
         raise ValueError("ref and test need the same number of frames")
     if out is None:
@@ -309,14 +331,8 @@ def jam_evaluate_stream(frames, planes, n: int, r: int, quant_step: int = 0, coe
     _need_cuda(frames, torch.uint8, "frames")
     nf = frames.shape[0]
     # every byte the kernel touches must lie inside the tensors
-    for name, buf in (("frames", frames), ("recon", recon)):
-        if buf is None:
-            continue
-        if buf.dim() != 2 or buf.stride(1) != 1 or buf.shape[0] != nf:
-            raise ValueError(f"{name} must be (n_frames, frame_bytes) with unit inner stride")
-        for off, h, w, pitch in planes:
-            if h >= 1 and w >= 1 and off + (h - 1) * pitch + w > buf.shape[1]:
-                raise ValueError(f"a plane reaches past the end of a frame of {name}")
+    _check_frames("frames", frames, planes, nf)
+    _check_frames("recon", recon, planes, nf)
     if sse is None:
         sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
     elif sse.numel() < nf * len(planes):
@@ -343,14 +359,8 @@ def evaluate_inverse(frames, planes, T, r: int, recon=None, sse=None, stream=Non
     import torch
     _need_cuda(frames, torch.uint8, "frames")
     nf = frames.shape[0]
-    for name, buf in (("frames", frames), ("recon", recon)):
-        if buf is None:
-            continue
-        if buf.dim() != 2 or buf.stride(1) != 1 or buf.shape[0] != nf:
-            raise ValueError(f"{name} must be (n_frames, frame_bytes) with unit inner stride")
-        for off, h, w, pitch in planes:
-            if off + (h - 1) * pitch + w > buf.shape[1]:
-                raise ValueError(f"a plane reaches past the end of a frame of {name}")
+    _check_frames("frames", frames, planes, nf)
+    _check_frames("recon", recon, planes, nf)
     if recon is not None:
         _need_cuda(recon, torch.uint8, "recon")
     t = np.ascontiguousarray(np.asarray(T, dtype=np.int8).reshape(64))
@@ -639,6 +649,8 @@ def filter_apply(packed, frames, planes, out=None, orig=None, stream=None):
     nf = frames.shape[0]
     if out is None:
         out = torch.zeros_like(frames)
+    for name, buf in (("frames", frames), ("out", out), ("orig", orig)):
+        _check_frames(name, buf, planes, nf)
     sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device) if orig is not None else None
     arr = planes_struct(planes)
     _check(lib().adct_filter_apply(_ptr(packed), _ptr(frames), frames.stride(0), nf, arr, len(planes), _ptr(out),
@@ -652,6 +664,8 @@ def filter_select(sse_filtered, sse_reference, plain, planes, out, keep=None, st
     the plain reconstruction copied into out.  Returns the keep flags (uint8)."""
     import torch
     nf = plain.shape[0]
+    _check_frames("plain", plain, planes, nf)
+    _check_frames("out", out, planes, nf)
     if keep is None:
         keep = torch.empty(nf, dtype=torch.uint8, device=plain.device)
     arr = planes_struct(planes)
