@@ -217,46 +217,18 @@ __global__ __launch_bounds__(256) void k_filter(const uint2 *vec, const uint32_t
 
 // ------------------------------------------------------------ top-k scan
 
-// Bin edges of the angle histogram: 8 bins per octave of u = 1 - cos.  With
-// u = (1 + f) 2^e, -8 log2 u = -8 e - 8 log2(1 + f), and 8 log2(1 + f) passes an
-// integer i where 1 + f passes 2^(i/8); kOctFrac[i] holds the 52 fraction bits
-// of 2^(i/8).  The histogram and the collection use the same edges, and the host
-// ranks the collected candidates exactly, so the edges need only be fixed and
-// monotone.
-struct OctFrac {
-    unsigned long long f[8];
-};
-constexpr double csqrt(double a) {
-    double x = a;
-    for (int i = 0; i < 64; ++i) x = 0.5 * (x + a / x);
-    return x;
-}
-constexpr OctFrac make_oct_frac() {
-    OctFrac t{};
-    const double r8 = csqrt(csqrt(csqrt(2.0)));           // 2^(1/8)
-    double x = 1.0;
-    for (int i = 0; i < 8; ++i) {
-        t.f[i] = (unsigned long long)((x - 1.0) * 4503599627370496.0);   // (2^(i/8) - 1) 2^52
-        x *= r8;
-    }
-    return t;
-}
-__device__ constexpr OctFrac kOctFrac = make_oct_frac();
-
-// floor(-8 log2(1 - c)) truncated toward zero (so angles past 90 degrees give
-// -1 or 0), clamped to the last bin; c >= 1 is the last bin
+// Bins of the angle histogram: 8 per octave of u = 1 - cos, read off the float64
+// representation of u: its biased exponent E and the top three fraction bits
+// t give key = 8 E + t, monotone in u, and bin = 8183 - key runs 0..7 over
+// [1/2, 1), 8..15 over [1/4, 1/2), and so on (u >= 1, angles of 90 degrees or
+// more, gives a negative bin, which is not counted).  The histogram and the
+// collection use the same bins, and the host ranks the collected candidates
+// exactly, so the edges need only be fixed and monotone.  c >= 1 is the last bin.
 __device__ __forceinline__ int angle_bin(double c) {
     const double u = 1.0 - c;
     if (!(u > 0.0)) return kHistBins - 1;
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(u);
-    const int e = int((bits >> 52) & 0x7ffu) - 1023;     // u >= 2^-53 is normal
-    const unsigned long long f = bits & 0xfffffffffffffull;
-    int j = 0;
-#pragma unroll
-    for (int i = 1; i < 8; ++i) j += f >= kOctFrac.f[i] ? 1 : 0;
-    int b;
-    if (e < 0) b = -8 * e - (f != 0 ? j + 1 : 0);      // positive: floor
-    else b = (e == 0 && j == 0) ? 0 : -1;              // u in [1, 2]: -8 log2 u in [-8, 0]
+    const uint32_t hi = uint32_t((unsigned long long)__double_as_longlong(u) >> 32);
+    const int b = 8183 - int(hi >> 17);
     return b >= kHistBins ? kHistBins - 1 : b;
 }
 
