@@ -301,7 +301,9 @@ typedef enum { ADCT_SEARCH_CLOSURE = 0, ADCT_SEARCH_CANONICAL = 1 } adct_search_
  *                 branch) paths
  * Each search state keeps its feasible list (space indices, 4 bytes each) on the
  * device for one depth; ADCT_ERANGE if a depth's lists would pass 32 GB.
- * Synchronises `stream`; allocates and frees its own device scratch. */
+ * Synchronises `stream`.  The enumerated space lives in grow-only device buffers
+ * kept per device until the process ends; searches on one device take a lock
+ * and run one at a time (this and adct_search_topk). */
 adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8_t *orders,
                                   int n_orders, int fix_rows_1_5, adct_matrix *out, int cap_out,
                                   int *n_out, double *angles_out, int64_t *leaves_out,
@@ -313,7 +315,8 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
  * canonical index.  primitive != 0 keeps only vectors whose entries have gcd 1
  * (a positive multiple of a row gives the same normalised row).
  *   vec_out  host int8 [8][k][8];  idx_out host [8][k] canonical indices;
- *   cos_out  host [8][k].  Synchronises `stream`. */
+ *   cos_out  host [8][k].  Synchronises `stream`; shares the per-device search
+ *   buffers and lock of adct_derive_transform. */
 adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8_t *vec_out,
                              int64_t *idx_out, double *cos_out, adct_stream_t stream);
 

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,7 @@ struct DctRows {
 // base b <= 9, umulhi(idx, ceil(2^32 / b)) is the exact quotient.
 struct Digits {
     unsigned long long packed;
+    unsigned long long primes;   // 4 bits per digit: value odd, not a multiple of 3, of 5, of 7
     uint32_t magic;
 };
 
@@ -107,27 +109,29 @@ __global__ void k_enum(int b, Digits dg, int64_t n, uint2 *vec, uint8_t *prim) {
     if (i >= n) return;
     uint32_t idx = uint32_t(i + 1);                  // canonical index; 0 is the zero vector
     int v[8];
+    uint32_t dig[8];
 #pragma unroll
     for (int e = 7; e >= 0; --e) {                   // first coordinate most significant
         const uint32_t q = __umulhi(idx, dg.magic);
         const uint32_t d = idx - q * uint32_t(b);
+        dig[e] = d;
         v[e] = int((dg.packed >> (5 * d)) & 31u) - 16;
         idx = q;
     }
     uint32_t lo = 0, hi = 0;
-    bool odd = false, non3 = false, non5 = false, non7 = false;
+#pragma unroll
     for (int e = 0; e < 8; ++e) {
         const uint32_t byte = uint32_t(uint8_t(int8_t(v[e])));
         if (e < 4) lo |= byte << (8 * e); else hi |= byte << (8 * (e - 4));
-        odd |= (v[e] & 1) != 0;
-        non3 |= (v[e] % 3) != 0;
-        non5 |= (v[e] % 5) != 0;
-        non7 |= (v[e] % 7) != 0;
     }
     vec[i] = make_uint2(lo, hi);
     // gcd of the entries is 1 exactly when no prime divides all of them; the
-    // entries are within +-8, so only 2, 3, 5 and 7 can
-    prim[i] = uint8_t(odd && non3 && non5 && non7);
+    // entries are within +-8, so only 2, 3, 5 and 7 can: OR the digits'
+    // "not divisible" bits and require all four
+    uint32_t nd = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) nd |= uint32_t(dg.primes >> (4 * dig[e])) & 15u;
+    prim[i] = uint8_t(nd == 15u);
 }
 
 // ------------------------------------------------------------ greedy queries
@@ -232,23 +236,33 @@ __device__ __forceinline__ int angle_bin(double c) {
     return b >= kHistBins ? kHistBins - 1 : b;
 }
 
+// The histogram pass also leaves each candidate's eight bins as bytes (bin + 1
+// clamped to [0, 255]; 0 for a skipped candidate or an angle of 90 degrees or
+// more), so the collection pass compares bytes and computes cosines only for
+// the few candidates it keeps.
 __global__ __launch_bounds__(256) void k_hist(int64_t n, const uint2 *vec, const uint8_t *prim, int primitive,
-                                             const double *invt, const DctRows rows, unsigned *hist) {
+                                             const double *invt, const DctRows rows, unsigned *hist,
+                                             uint2 *codes) {
     __shared__ unsigned h[8 * kHistBins];
     for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
-        if (primitive && !prim[i]) continue;
-        const uint2 p = vec[i];
-        int v[8];
-        unpack8(p, v);
-        const double inv = inv_norm(p, invt);
+        uint32_t c0 = 0, c1 = 0;
+        if (!(primitive && !prim[i])) {
+            const uint2 p = vec[i];
+            int v[8];
+            unpack8(p, v);
+            const double inv = inv_norm(p, invt);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int bn = angle_bin(cos_row(v, inv, rows, r));
-            if (bn >= 0) atomicAdd(&h[r * kHistBins + bn], 1u);
+            for (int r = 0; r < 8; ++r) {
+                const int bn = angle_bin(cos_row(v, inv, rows, r));
+                if (bn >= 0) atomicAdd(&h[r * kHistBins + bn], 1u);
+                const uint32_t code = uint32_t(min(max(bn + 1, 0), 255));
+                if (r < 4) c0 |= code << (8 * r); else c1 |= code << (8 * (r - 4));
+            }
         }
+        codes[i] = make_uint2(c0, c1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x)
@@ -282,6 +296,38 @@ __global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const uint2 *ve
                     out_idx[th.off[r] + int64_t(pos)] = i;
                     out_cos[th.off[r] + int64_t(pos)] = c;
                 }
+            }
+        }
+    }
+}
+
+// Collection from the stored bins: a candidate joins row r's list when its byte
+// reaches th.bin[r] + 1 (the same test as angle_bin >= th.bin[r] while
+// th.bin[r] <= 254; the host uses the recomputing kernel otherwise).
+__global__ __launch_bounds__(256) void k_topk_collect_codes(int64_t n, const uint2 *codes, const uint2 *vec,
+                                                           const double *invt, const DctRows rows,
+                                                           Thresholds th, int64_t *out_idx, double *out_cos,
+                                                           unsigned long long *count) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const uint2 cw = codes[i];
+        uint32_t hit = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int code = int(((r < 4 ? cw.x : cw.y) >> (8 * (r & 3))) & 0xffu);
+            hit |= (code >= th.bin[r] + 1) ? (1u << r) : 0u;
+        }
+        if (!hit) continue;
+        const uint2 p = vec[i];
+        int v[8];
+        unpack8(p, v);
+        const double inv = inv_norm(p, invt);
+        for (int r = 0; r < 8; ++r) {
+            if (!((hit >> r) & 1u)) continue;
+            const unsigned long long pos = atomicAdd(count + r, 1ull);
+            if (int64_t(pos) < th.cap[r]) {
+                out_idx[th.off[r] + int64_t(pos)] = i;
+                out_cos[th.off[r] + int64_t(pos)] = cos_row(v, inv, rows, r);
             }
         }
     }
@@ -326,12 +372,42 @@ adct_status dalloc(DevBuf &b, size_t count) {
     return ADCT_OK;
 }
 
+// Device buffers the searches reuse from call to call (the enumerated space,
+// its primitive flags, the top-k bin codes): grow-only, per device, kept until
+// the process ends.  A search holds its device's lock from the space's
+// enumeration until it has synchronised its stream and returned, so searches on
+// one device run one at a time.
+struct SearchCache {
+    std::mutex lock;
+    void *slot[3] = {nullptr, nullptr, nullptr};
+    size_t bytes[3] = {0, 0, 0};
+};
+constexpr int kCacheDevices = 64;
+SearchCache g_cache[kCacheDevices];
+
 struct Space {
     int b = 0;
     int8_t digits[9] = {};
     int64_t n = 0;
-    DevBuf vec, prim, inv;
+    std::unique_lock<std::mutex> hold;    // the device's cache, for the whole search
+    SearchCache *cache = nullptr;
+    void *vec = nullptr, *prim = nullptr;
+    DevBuf inv;
 };
+
+// buffer `slot` of the held cache with at least `bytes` bytes
+adct_status cached(Space &sp, int slot, size_t bytes, void **out) {
+    SearchCache &c = *sp.cache;
+    if (c.bytes[slot] < bytes) {
+        if (c.slot[slot]) ADCT_HIP(hipFree(c.slot[slot]));
+        c.slot[slot] = nullptr;
+        c.bytes[slot] = 0;
+        ADCT_HIP(hipMalloc(&c.slot[slot], bytes));
+        c.bytes[slot] = bytes;
+    }
+    *out = c.slot[slot];
+    return ADCT_OK;
+}
 
 adct_status canonical_digits(const int8_t *P, int nP, int8_t *out, int *b) {
     if (!P) return fail(ADCT_EINVAL, "P is null");
@@ -359,16 +435,28 @@ adct_status build_space(const int8_t *P, int nP, Space &sp, hipStream_t s) {
     for (int i = 0; i < 8; ++i) total *= sp.b;
     sp.n = total - 1;
     if (sp.n < 1) return fail(ADCT_ERANGE, "search space is empty");
-    if ((st = dalloc<uint2>(sp.vec, sp.n))) return st;
-    if ((st = dalloc<uint8_t>(sp.prim, sp.n))) return st;
+    int dev = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kCacheDevices) return fail(ADCT_ENOTSUP, "device index beyond the search cache");
+    sp.cache = &g_cache[dev];
+    sp.hold = std::unique_lock<std::mutex>(sp.cache->lock);
+    if ((st = cached(sp, 0, size_t(sp.n) * sizeof(uint2), &sp.vec))) return st;
+    if ((st = cached(sp, 1, size_t(sp.n), &sp.prim))) return st;
     Digits dg;
     dg.packed = 0;
-    for (int i = 0; i < sp.b; ++i) dg.packed |= (unsigned long long)(sp.digits[i] + 16) << (5 * i);
+    dg.primes = 0;
+    for (int i = 0; i < sp.b; ++i) {
+        const int v = sp.digits[i];
+        dg.packed |= (unsigned long long)(v + 16) << (5 * i);
+        const unsigned long long m = (v % 2 != 0 ? 1u : 0u) | (v % 3 != 0 ? 2u : 0u) | (v % 5 != 0 ? 4u : 0u) |
+                                     (v % 7 != 0 ? 8u : 0u);
+        dg.primes |= m << (4 * i);
+    }
     dg.magic = uint32_t(((uint64_t(1) << 32) + uint64_t(sp.b) - 1) / uint64_t(sp.b));   // ceil(2^32 / b)
     if (sp.b == 1) dg.magic = 0xffffffffu;           // b = 1 never divides (only the zero vector)
     const int64_t blocks = (sp.n + 255) / 256;
     hipLaunchKernelGGL(k_enum, dim3(unsigned(blocks)), dim3(256), 0, s, sp.b, dg, sp.n,
-                       (uint2 *)sp.vec.p, (uint8_t *)sp.prim.p);
+                       (uint2 *)sp.vec, (uint8_t *)sp.prim);
     ADCT_HIP(hipGetLastError());
     if ((st = dalloc<double>(sp.inv, kMaxNorm2 + 1))) return st;
     hipLaunchKernelGGL(k_inv_table, dim3((kMaxNorm2 + 256) / 256), dim3(256), 0, s, (double *)sp.inv.p);
@@ -483,7 +571,7 @@ adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vecto
     for (int y0 = 0; y0 < nq; y0 += 65535) {
         const int ny = std::min(nq - y0, 65535);
         hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, lists,
-                           (const uint2 *)sp.vec.p, (const double *)sp.inv.p, dct_rows(),
+                           (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(),
                            (unsigned long long *)dbest.p + y0);
         ADCT_HIP(hipGetLastError());
     }
@@ -495,7 +583,7 @@ adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vecto
         for (int y0 = 0; y0 < nq; y0 += 65535) {
             const int ny = std::min(nq - y0, 65535);
             hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0,
-                               lists, (const uint2 *)sp.vec.p, (const double *)sp.inv.p, dct_rows(),
+                               lists, (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(),
                                (const unsigned long long *)dbest.p + y0, cap,
                                (int64_t *)didx.p + int64_t(y0) * cap, (double *)dcos.p + int64_t(y0) * cap,
                                (int *)dcount.p + y0);
@@ -631,7 +719,7 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
     if ((st = dalloc<int>(dlen, 1))) return st;
     ADCT_HIP(hipMemsetAsync(dlen.p, 0, sizeof(int), s));
     hipLaunchKernelGGL(k_root_list, dim3(unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048))), dim3(256), 0, s,
-                       sp.n, (const uint2 *)sp.vec.p, pack8(r0), pack8(r4), fix_rows_1_5 ? 2 : 0,
+                       sp.n, (const uint2 *)sp.vec, pack8(r0), pack8(r4), fix_rows_1_5 ? 2 : 0,
                        (uint32_t *)lists.p, (int *)dlen.p);
     ADCT_HIP(hipGetLastError());
     int root_len = 0;
@@ -717,7 +805,7 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
             const unsigned chunks = unsigned(std::min<int64_t>((maxlen + 255) / 256, 64));
             for (int y0 = 0; y0 < nj; y0 += 65535) {
                 const int ny = std::min(nj - y0, 65535);
-                hipLaunchKernelGGL(k_filter, dim3(chunks, ny), dim3(256), 0, s, (const uint2 *)sp.vec.p,
+                hipLaunchKernelGGL(k_filter, dim3(chunks, ny), dim3(256), 0, s, (const uint2 *)sp.vec,
                                    (const uint32_t *)lists.p, (const FilterJob *)dj.p + y0, (uint32_t *)nl.p,
                                    (int *)dl.p + y0);
                 ADCT_HIP(hipGetLastError());
@@ -757,11 +845,13 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     if (st) return st;
     DevBuf dhist;
     if ((st = dalloc<unsigned>(dhist, 8 * kHistBins))) return st;
+    void *codes = nullptr;
+    if ((st = cached(sp, 2, size_t(sp.n) * sizeof(uint2), &codes))) return st;
     ADCT_HIP(hipMemsetAsync(dhist.p, 0, sizeof(unsigned) * 8 * kHistBins, s));
     const unsigned grid = unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048));
-    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec.p,
-                       (const uint8_t *)sp.prim.p, primitive, (const double *)sp.inv.p, dct_rows(),
-                       (unsigned *)dhist.p);
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec,
+                       (const uint8_t *)sp.prim, primitive, (const double *)sp.inv.p, dct_rows(),
+                       (unsigned *)dhist.p, (uint2 *)codes);
     ADCT_HIP(hipGetLastError());
     std::vector<unsigned> hist(8 * kHistBins);
     ADCT_HIP(hipMemcpyAsync(hist.data(), dhist.p, sizeof(unsigned) * hist.size(), hipMemcpyDeviceToHost, s));
@@ -788,10 +878,16 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     if ((st = dalloc<double>(dcos, total))) return st;
     if ((st = dalloc<unsigned long long>(dcnt, 8))) return st;
     ADCT_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(unsigned long long) * 8, s));
-    hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec.p,
-                       (const uint8_t *)sp.prim.p, primitive, (const double *)sp.inv.p, dct_rows(), th,
-                       (int64_t *)didx.p,
-                       (double *)dcos.p, (unsigned long long *)dcnt.p);
+    bool bytes_ok = true;
+    for (int r = 0; r < 8; ++r) bytes_ok &= th.bin[r] <= 254;
+    if (bytes_ok)
+        hipLaunchKernelGGL(k_topk_collect_codes, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)codes,
+                           (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(), th, (int64_t *)didx.p,
+                           (double *)dcos.p, (unsigned long long *)dcnt.p);
+    else
+        hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec,
+                           (const uint8_t *)sp.prim, primitive, (const double *)sp.inv.p, dct_rows(), th,
+                           (int64_t *)didx.p, (double *)dcos.p, (unsigned long long *)dcnt.p);
     ADCT_HIP(hipGetLastError());
     std::vector<int64_t> idx(std::max<int64_t>(total, 1));
     std::vector<double> cs(std::max<int64_t>(total, 1));

@@ -79,3 +79,26 @@ def test_coding_gain_sweep_matches_oracle(cuda):
     for i, c in enumerate(chats):
         want = np.array([Me.unified_coding_gain(c, float(p)) for p in rhos])
         np.testing.assert_allclose(got[i], want, rtol=0, atol=1e-9)
+
+
+def test_inverse_decoder_full_4k_frame(cuda):
+    """One 3840 x 2160 4:2:0 frame in the benchmark's launch configuration (SDCT,
+    r = 10): every plane's squared error and the luma reconstruction."""
+    import torch
+    spec = video_spec(n_frames=1)
+    bases = video_base_planes(spec)
+    frame = video_frame(spec, bases, 0)
+    planes, off = [], 0
+    for h, w in spec.plane_shapes:
+        planes.append((off, h, w, w))
+        off += h * w
+    dev = _dev(frame.reshape(1, -1), cuda)
+    rec = torch.zeros_like(dev)
+    sse = A.evaluate_inverse(dev, planes, M.t_sdct(), 10, recon=rec).cpu().numpy()
+    got = rec.cpu().numpy()[0]
+    for p, (o, h, w, _) in enumerate(planes):
+        img = frame[o:o + h * w].reshape(h, w)
+        want = N.evaluate(img, M.t_sdct(), 10)
+        assert int(sse[0, p]) == want["sse"], p
+        if p == 0:
+            assert np.array_equal(got[o:o + h * w].reshape(h, w), want["rec"])
