@@ -377,10 +377,14 @@ adct_status dalloc(DevBuf &b, size_t count) {
 // the process ends.  A search holds its device's lock from the space's
 // enumeration until it has synchronised its stream and returned, so searches on
 // one device run one at a time.
+// slots: 0 space, 1 primitive flags, 2 top-k bin bytes, 3-7 closure queries,
+// maxima, counts, collected indices and cosines, 8-9 feasible-list arenas of
+// two consecutive depths, 10-11 filter jobs and list lengths
+constexpr int kCacheSlots = 12;
 struct SearchCache {
     std::mutex lock;
-    void *slot[3] = {nullptr, nullptr, nullptr};
-    size_t bytes[3] = {0, 0, 0};
+    void *slot[kCacheSlots] = {};
+    size_t bytes[kCacheSlots] = {};
 };
 constexpr int kCacheDevices = 64;
 SearchCache g_cache[kCacheDevices];
@@ -394,6 +398,15 @@ struct Space {
     void *vec = nullptr, *prim = nullptr;
     DevBuf inv;
 };
+
+adct_status cached(Space &sp, int slot, size_t bytes, void **out);
+template <class T>
+adct_status cached_n(Space &sp, int slot, int64_t count, T **out) {
+    void *p = nullptr;
+    adct_status st = cached(sp, slot, size_t(std::max<int64_t>(count, 1)) * sizeof(T), &p);
+    *out = static_cast<T *>(p);
+    return st;
+}
 
 // buffer `slot` of the held cache with at least `bytes` bytes
 adct_status cached(Space &sp, int slot, size_t bytes, void **out) {
@@ -551,18 +564,21 @@ struct MatKey {
 
 // Answer a batch of queries: per query the collected window (or none when the
 // feasible set is empty).
-adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vector<Query> &qs,
+adct_status run_queries(Space &sp, const uint32_t *lists, const std::vector<Query> &qs,
                         std::vector<std::vector<Cand>> &res, std::vector<char> &dead, hipStream_t s) {
     const int nq = int(qs.size());
     res.assign(nq, {});
     dead.assign(nq, 0);
     if (nq == 0) return ADCT_OK;
     int cap = 64;
-    DevBuf dq, dbest, dcount;
+    Query *dq_p = nullptr;
+    unsigned long long *dbest_p = nullptr;
+    int *dcount_p = nullptr;
     adct_status st;
-    if ((st = dalloc<Query>(dq, nq))) return st;
-    if ((st = dalloc<unsigned long long>(dbest, nq))) return st;
-    if ((st = dalloc<int>(dcount, nq))) return st;
+    if ((st = cached_n(sp, 3, nq, &dq_p))) return st;
+    if ((st = cached_n(sp, 4, nq, &dbest_p))) return st;
+    if ((st = cached_n(sp, 5, nq, &dcount_p))) return st;
+    struct { void *p; } dq{dq_p}, dbest{dbest_p}, dcount{dcount_p};
     ADCT_HIP(hipMemcpyAsync(dq.p, qs.data(), sizeof(Query) * nq, hipMemcpyHostToDevice, s));
     ADCT_HIP(hipMemsetAsync(dbest.p, 0, sizeof(unsigned long long) * nq, s));
     int64_t maxlen = 1;
@@ -576,9 +592,11 @@ adct_status run_queries(const Space &sp, const uint32_t *lists, const std::vecto
         ADCT_HIP(hipGetLastError());
     }
     for (;;) {
-        DevBuf didx, dcos;
-        if ((st = dalloc<int64_t>(didx, int64_t(nq) * cap))) return st;
-        if ((st = dalloc<double>(dcos, int64_t(nq) * cap))) return st;
+        int64_t *didx_p = nullptr;
+        double *dcos_p = nullptr;
+        if ((st = cached_n(sp, 6, int64_t(nq) * cap, &didx_p))) return st;
+        if ((st = cached_n(sp, 7, int64_t(nq) * cap, &dcos_p))) return st;
+        struct { void *p; } didx{didx_p}, dcos{dcos_p};
         ADCT_HIP(hipMemsetAsync(dcount.p, 0, sizeof(int) * nq, s));
         for (int y0 = 0; y0 < nq; y0 += 65535) {
             const int ny = std::min(nq - y0, 65535);
@@ -714,9 +732,12 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
         root.set[0] = root.set[4] = true;
     }
     // the root's feasible list: every candidate orthogonal to the fixed rows
-    DevBuf lists, dlen;
-    if ((st = dalloc<uint32_t>(lists, sp.n))) return st;
-    if ((st = dalloc<int>(dlen, 1))) return st;
+    int cur_slot = 8, nxt_slot = 9;
+    uint32_t *lists_p = nullptr;
+    int *dlen_p = nullptr;
+    if ((st = cached_n(sp, cur_slot, sp.n, &lists_p))) return st;
+    if ((st = cached_n(sp, 11, 1, &dlen_p))) return st;
+    struct { void *p; } lists{lists_p}, dlen{dlen_p};
     ADCT_HIP(hipMemsetAsync(dlen.p, 0, sizeof(int), s));
     hipLaunchKernelGGL(k_root_list, dim3(unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048))), dim3(256), 0, s,
                        sp.n, (const uint2 *)sp.vec, pack8(r0), pack8(r4), fix_rows_1_5 ? 2 : 0,
@@ -794,10 +815,13 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
             if (total > (int64_t(1) << 33))
                 return fail(ADCT_ERANGE, "the next depth's feasible lists would exceed 32 GB (fix rows 1 and 5, "
                                          "or search fewer orders)");
-            DevBuf nl, dj, dl;
-            if ((st = dalloc<uint32_t>(nl, std::max<int64_t>(total, 1)))) return st;
-            if ((st = dalloc<FilterJob>(dj, nj))) return st;
-            if ((st = dalloc<int>(dl, nj))) return st;
+            uint32_t *nl_p = nullptr;
+            FilterJob *dj_p = nullptr;
+            int *dl_p = nullptr;
+            if ((st = cached_n(sp, nxt_slot, total, &nl_p))) return st;
+            if ((st = cached_n(sp, 10, nj, &dj_p))) return st;
+            if ((st = cached_n(sp, 11, nj, &dl_p))) return st;
+            struct { void *p; } nl{nl_p}, dj{dj_p}, dl{dl_p};
             ADCT_HIP(hipMemcpyAsync(dj.p, jobs.data(), sizeof(FilterJob) * nj, hipMemcpyHostToDevice, s));
             ADCT_HIP(hipMemsetAsync(dl.p, 0, sizeof(int) * nj, s));
             int64_t maxlen = 1;
@@ -817,7 +841,8 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
                 next[j].loff = jobs[j].out_off;
                 next[j].llen = lens[j];
             }
-            std::swap(lists.p, nl.p);     // the parent arena is freed with nl
+            lists.p = nl.p;               // the parent arena is reused two depths on
+            std::swap(cur_slot, nxt_slot);
         }
         frontier.swap(next);
     }
