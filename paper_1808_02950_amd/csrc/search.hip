@@ -190,15 +190,35 @@ __global__ __launch_bounds__(256) void k_qcollect(const Query *qs, const uint32_
 // candidate just chosen (the chosen one itself drops out: |v|^2 > 0).  Entry
 // order inside a list follows the atomics and does not matter: the queries take
 // a maximum and a window, and the host orders what they collect.
+// Append for a whole wave with one atomic: the lanes that keep an entry take
+// consecutive slots after the wave's base (ballot, popcount, lane prefix).  Every
+// lane of the wave calls it.
+__device__ __forceinline__ int64_t wave_append(int *counter, bool keep) {
+    const unsigned long long mask = __ballot(keep);
+    if (!mask) return -1;
+    const int lane = int(threadIdx.x & 63);
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    return keep ? int64_t(base) + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+}
+
+// the loops run a wave-uniform number of rounds so every lane reaches the ballot
 __global__ __launch_bounds__(256) void k_root_list(int64_t n, const uint2 *vec, uint2 f0, uint2 f1, int nfixed,
                                                   uint32_t *out, int *len) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const uint2 p = vec[i];
-        bool ok = true;
-        if (nfixed > 0) ok &= sdot8(p, f0) == 0;
-        if (nfixed > 1) ok &= sdot8(p, f1) == 0;
-        if (ok) out[atomicAdd(len, 1)] = uint32_t(i);
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int64_t first = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+    for (int64_t w = first; w < n; w += stride) {
+        const int64_t i = w + (threadIdx.x & 63);
+        bool ok = i < n;
+        if (ok) {
+            const uint2 p = vec[i];
+            if (nfixed > 0) ok &= sdot8(p, f0) == 0;
+            if (nfixed > 1) ok &= sdot8(p, f1) == 0;
+        }
+        const int64_t pos = wave_append(len, ok);
+        if (ok) out[pos] = uint32_t(i);
     }
 }
 
@@ -212,10 +232,18 @@ __global__ __launch_bounds__(256) void k_filter(const uint2 *vec, const uint32_t
                                                uint32_t *out, int *lens) {
     const FilterJob j = jobs[blockIdx.y];
     const uint2 c = vec[j.chosen];
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < j.in_len;
-         t += int64_t(gridDim.x) * blockDim.x) {
-        const uint32_t i = in[j.in_off + t];
-        if (sdot8(vec[i], c) == 0) out[j.out_off + atomicAdd(lens + blockIdx.y, 1)] = i;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int64_t first = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+    for (int64_t w = first; w < j.in_len; w += stride) {
+        const int64_t t = w + (threadIdx.x & 63);
+        uint32_t i = 0;
+        bool keep = t < j.in_len;
+        if (keep) {
+            i = in[j.in_off + t];
+            keep = sdot8(vec[i], c) == 0;
+        }
+        const int64_t pos = wave_append(lens + blockIdx.y, keep);
+        if (keep) out[j.out_off + pos] = i;
     }
 }
 
