@@ -606,17 +606,16 @@ adct_status run_queries(Space &sp, const uint32_t *lists, const std::vector<Quer
     if ((st = cached_n(sp, 3, nq, &dq_p))) return st;
     if ((st = cached_n(sp, 4, nq, &dbest_p))) return st;
     if ((st = cached_n(sp, 5, nq, &dcount_p))) return st;
-    struct { void *p; } dq{dq_p}, dbest{dbest_p}, dcount{dcount_p};
-    ADCT_HIP(hipMemcpyAsync(dq.p, qs.data(), sizeof(Query) * nq, hipMemcpyHostToDevice, s));
-    ADCT_HIP(hipMemsetAsync(dbest.p, 0, sizeof(unsigned long long) * nq, s));
+    ADCT_HIP(hipMemcpyAsync(dq_p, qs.data(), sizeof(Query) * nq, hipMemcpyHostToDevice, s));
+    ADCT_HIP(hipMemsetAsync(dbest_p, 0, sizeof(unsigned long long) * nq, s));
     int64_t maxlen = 1;
     for (const Query &q : qs) maxlen = std::max<int64_t>(maxlen, q.len);
     const unsigned chunks = unsigned(std::min<int64_t>((maxlen + 255) / 256, 64));
     for (int y0 = 0; y0 < nq; y0 += 65535) {
         const int ny = std::min(nq - y0, 65535);
-        hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0, lists,
+        hipLaunchKernelGGL(k_qmax, dim3(chunks, ny), dim3(256), 0, s, dq_p + y0, lists,
                            (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(),
-                           (unsigned long long *)dbest.p + y0);
+                           dbest_p + y0);
         ADCT_HIP(hipGetLastError());
     }
     for (;;) {
@@ -624,21 +623,20 @@ adct_status run_queries(Space &sp, const uint32_t *lists, const std::vector<Quer
         double *dcos_p = nullptr;
         if ((st = cached_n(sp, 6, int64_t(nq) * cap, &didx_p))) return st;
         if ((st = cached_n(sp, 7, int64_t(nq) * cap, &dcos_p))) return st;
-        struct { void *p; } didx{didx_p}, dcos{dcos_p};
-        ADCT_HIP(hipMemsetAsync(dcount.p, 0, sizeof(int) * nq, s));
+        ADCT_HIP(hipMemsetAsync(dcount_p, 0, sizeof(int) * nq, s));
         for (int y0 = 0; y0 < nq; y0 += 65535) {
             const int ny = std::min(nq - y0, 65535);
-            hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, (const Query *)dq.p + y0,
+            hipLaunchKernelGGL(k_qcollect, dim3(chunks, ny), dim3(256), 0, s, dq_p + y0,
                                lists, (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(),
-                               (const unsigned long long *)dbest.p + y0, cap,
-                               (int64_t *)didx.p + int64_t(y0) * cap, (double *)dcos.p + int64_t(y0) * cap,
-                               (int *)dcount.p + y0);
+                               dbest_p + y0, cap,
+                               didx_p + int64_t(y0) * cap, dcos_p + int64_t(y0) * cap,
+                               dcount_p + y0);
             ADCT_HIP(hipGetLastError());
         }
         std::vector<int> cnt(nq);
         std::vector<unsigned long long> best(nq);
-        ADCT_HIP(hipMemcpyAsync(cnt.data(), dcount.p, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
-        ADCT_HIP(hipMemcpyAsync(best.data(), dbest.p, sizeof(unsigned long long) * nq, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(cnt.data(), dcount_p, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(best.data(), dbest_p, sizeof(unsigned long long) * nq, hipMemcpyDeviceToHost, s));
         ADCT_HIP(hipStreamSynchronize(s));
         const int need = *std::max_element(cnt.begin(), cnt.end());
         if (need > cap) {                    // window larger than the buffer: grow and redo
@@ -647,8 +645,8 @@ adct_status run_queries(Space &sp, const uint32_t *lists, const std::vector<Quer
         }
         std::vector<int64_t> idx(int64_t(nq) * cap);
         std::vector<double> cs(int64_t(nq) * cap);
-        ADCT_HIP(hipMemcpyAsync(idx.data(), didx.p, sizeof(int64_t) * idx.size(), hipMemcpyDeviceToHost, s));
-        ADCT_HIP(hipMemcpyAsync(cs.data(), dcos.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(idx.data(), didx_p, sizeof(int64_t) * idx.size(), hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(cs.data(), dcos_p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
         ADCT_HIP(hipStreamSynchronize(s));
         for (int q = 0; q < nq; ++q) {
             if (best[q] == 0) {
@@ -765,14 +763,13 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
     int *dlen_p = nullptr;
     if ((st = cached_n(sp, cur_slot, sp.n, &lists_p))) return st;
     if ((st = cached_n(sp, 11, 1, &dlen_p))) return st;
-    struct { void *p; } lists{lists_p}, dlen{dlen_p};
-    ADCT_HIP(hipMemsetAsync(dlen.p, 0, sizeof(int), s));
+    ADCT_HIP(hipMemsetAsync(dlen_p, 0, sizeof(int), s));
     hipLaunchKernelGGL(k_root_list, dim3(unsigned(std::min<int64_t>((sp.n + 255) / 256, 2048))), dim3(256), 0, s,
                        sp.n, (const uint2 *)sp.vec, pack8(r0), pack8(r4), fix_rows_1_5 ? 2 : 0,
-                       (uint32_t *)lists.p, (int *)dlen.p);
+                       lists_p, dlen_p);
     ADCT_HIP(hipGetLastError());
     int root_len = 0;
-    ADCT_HIP(hipMemcpyAsync(&root_len, dlen.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    ADCT_HIP(hipMemcpyAsync(&root_len, dlen_p, sizeof(int), hipMemcpyDeviceToHost, s));
     ADCT_HIP(hipStreamSynchronize(s));
     root.loff = 0;
     root.llen = root_len;
@@ -795,7 +792,7 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
         }
         std::vector<std::vector<Cand>> res;
         std::vector<char> isdead;
-        if ((st = run_queries(sp, (const uint32_t *)lists.p, qs, res, isdead, s))) return st;
+        if ((st = run_queries(sp, lists_p, qs, res, isdead, s))) return st;
         std::vector<State> next;
         for (size_t q = 0; q < qs.size(); ++q) {
             const State &S = frontier[qmeta[q].first];
@@ -849,27 +846,26 @@ adct_status adct_derive_transform(const int8_t *P, int nP, int mode, const uint8
             if ((st = cached_n(sp, nxt_slot, total, &nl_p))) return st;
             if ((st = cached_n(sp, 10, nj, &dj_p))) return st;
             if ((st = cached_n(sp, 11, nj, &dl_p))) return st;
-            struct { void *p; } nl{nl_p}, dj{dj_p}, dl{dl_p};
-            ADCT_HIP(hipMemcpyAsync(dj.p, jobs.data(), sizeof(FilterJob) * nj, hipMemcpyHostToDevice, s));
-            ADCT_HIP(hipMemsetAsync(dl.p, 0, sizeof(int) * nj, s));
+            ADCT_HIP(hipMemcpyAsync(dj_p, jobs.data(), sizeof(FilterJob) * nj, hipMemcpyHostToDevice, s));
+            ADCT_HIP(hipMemsetAsync(dl_p, 0, sizeof(int) * nj, s));
             int64_t maxlen = 1;
             for (const FilterJob &j : jobs) maxlen = std::max<int64_t>(maxlen, j.in_len);
             const unsigned chunks = unsigned(std::min<int64_t>((maxlen + 255) / 256, 64));
             for (int y0 = 0; y0 < nj; y0 += 65535) {
                 const int ny = std::min(nj - y0, 65535);
                 hipLaunchKernelGGL(k_filter, dim3(chunks, ny), dim3(256), 0, s, (const uint2 *)sp.vec,
-                                   (const uint32_t *)lists.p, (const FilterJob *)dj.p + y0, (uint32_t *)nl.p,
-                                   (int *)dl.p + y0);
+                                   lists_p, dj_p + y0, nl_p,
+                                   dl_p + y0);
                 ADCT_HIP(hipGetLastError());
             }
             std::vector<int> lens(nj);
-            ADCT_HIP(hipMemcpyAsync(lens.data(), dl.p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
+            ADCT_HIP(hipMemcpyAsync(lens.data(), dl_p, sizeof(int) * nj, hipMemcpyDeviceToHost, s));
             ADCT_HIP(hipStreamSynchronize(s));
             for (int j = 0; j < nj; ++j) {
                 next[j].loff = jobs[j].out_off;
                 next[j].llen = lens[j];
             }
-            lists.p = nl.p;               // the parent arena is reused two depths on
+            lists_p = nl_p;               // the parent arena is reused two depths on
             std::swap(cur_slot, nxt_slot);
         }
         frontier.swap(next);
