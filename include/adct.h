@@ -55,7 +55,15 @@ typedef enum {
  *   T1, T2  the matrices the paper derives (Sec. 4.1); T1 is the proposed one
  *   LO      Lengwehasatit-Ortega, stored doubled (2 T_LO) so it is integral
  *   T6, T4  Cintra et al. 2014;  RDCT  rounded DCT  (Sec. 2, matrix table)
- *   CUSTOM  any int8 matrix with orthogonal rows, passed in `custom`. */
+ *   CUSTOM  a caller's int8 matrix with orthogonal rows, passed in `custom`
+ *           (e.g. one adct_derive_transform returned: derive T by Eq. (6),
+ *           then code with it, Sec. 3.5 and 6.1.1).  custom->n[k] must equal
+ *           (T T^T)_kk > 0 and T T^T must be diagonal, else ADCT_EINVAL.  It
+ *           runs kernels that read T at run time: the same results as a
+ *           built-in kernel for the same matrix, bit for bit.  Word limits:
+ *           lcm(n) <= 2^26 and every partial sum of the exact inverse below
+ *           2^61 (ADCT_EOVERFLOW); with a quantiser |Y| < 2^24 (ADCT_ERANGE).
+ * Every codec entry point ignores `custom` unless t == ADCT_CUSTOM. */
 typedef enum {
     ADCT_DCT = 0,
     ADCT_T1 = 1,
@@ -135,12 +143,19 @@ adct_status adct_encode_blocks(const uint8_t *img, int H, int W, int pitch,
                                adct_stream_t stream);
 
 /* Inverse of adct_encode_blocks (Sec. 6.1.1: A = C_hat^T B' C_hat, valid for
- * T with orthogonal rows).  Input is coef_int (integer transforms; Y or q as
- * written by encode) or coef_scaled (ADCT_DCT: B in float32); exactly one
- * must be non-null.  Output: `out` (device) H x W uint8 with pitch_out, the
- * reconstruction rounded half-to-even and clipped to [0, 255].  For integer
- * transforms with quant_step == 0 the reconstruction is exact (integer
- * arithmetic on the rational result). */
+ * T with orthogonal rows).  Exactly one input must be non-null:
+ *   coef_int    device int16 [n_blocks][r]: Y (quant_step == 0) or q as
+ *               written by encode (integer transforms; for ADCT_DCT the
+ *               quantised levels, quant_step > 0);
+ *   coef_scaled device float32 [n_blocks][r]: B itself, any transform, with
+ *               quant_step == 0 (ADCT_EINVAL otherwise); the inverse runs in
+ *               float64 (float32 for the exact DCT's matrix cores).
+ * Output: `out` (device) H x W uint8 with pitch_out, the reconstruction
+ * rounded half-to-even and clipped to [0, 255].  For integer transforms with
+ * coef_int and quant_step == 0 the reconstruction is exact (integer
+ * arithmetic on the rational result).  Coefficients that no 8-bit block
+ * produces may overflow the word sizes the bounds were checked for; the
+ * result for them is unspecified (no memory outside the buffers is touched). */
 adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled,
                                int H, int W, uint8_t *out, int pitch_out,
                                adct_transform_id t, const adct_matrix *custom,

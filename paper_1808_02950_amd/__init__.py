@@ -140,6 +140,56 @@ def _need_cuda(t, dtype, name):
         raise TypeError(f"{name} must be {dtype}")
 
 
+def _need_out(t, dtype, need: int, name: str):
+    """A caller-supplied buffer the library writes (or reads) as `need` elements
+    of `dtype` from its data pointer: a contiguous CUDA tensor of that dtype
+    with at least that many elements (None passes)."""
+    if t is None:
+        return
+    _need_cuda(t, dtype, name)
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < need:
+        raise ValueError(f"{name} needs at least {need} elements of {dtype}, has {t.numel()}")
+
+
+def _need_image(t, h: int, w: int, name: str):
+    """A caller-supplied 2-D uint8 image of exactly (h, w) with unit column
+    stride: the library addresses it as h rows of w bytes, stride(0) apart."""
+    if t is None:
+        return
+    import torch
+    _need_cuda(t, torch.uint8, name)
+    if t.dim() != 2 or tuple(t.shape) != (h, w) or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a ({h}, {w}) uint8 image with unit column stride")
+
+
+def _check_buffer(name, buf, planes):
+    """Every byte a kernel reaches through `planes` (offset, H, W, pitch) must
+    lie inside the contiguous tensor `buf`."""
+    if not buf.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    total = buf.numel()
+    for off, h, w, pitch in planes:
+        if off < 0 or h < 1 or w < 1 or pitch < w or off + (h - 1) * pitch + w > total:
+            raise ValueError(f"an image reaches outside {name}")
+
+
+def _matrix_arg(t):
+    """(transform id, Matrix or None): a name / id, or an 8x8 integer matrix,
+    which is passed as ADCT_CUSTOM."""
+    if isinstance(t, (str, int, np.integer)):
+        return _tid(t), None
+    m = np.asarray(t)
+    if m.shape != (8, 8) or not np.issubdtype(m.dtype, np.integer) or np.abs(m).max() > 127:
+        raise ValueError("a custom transform must be an 8x8 integer matrix with int8 entries")
+    return CUSTOM, _matrix_struct(m)
+
+
+def _mref(m):
+    return ctypes.byref(m) if m is not None else None
+
+
 def _check_frames(name, buf, planes, nf):
     """Every byte a kernel reads or writes through `planes` must lie inside the
     (n_frames, frame_bytes) tensor `buf` (None passes)."""
@@ -197,29 +247,45 @@ def n_blocks(h: int, w: int) -> int:
 def encode_blocks(img, t, r: int, quant_step: int = 0, want_int: bool = True,
                   want_scaled: bool = False, coef_int=None, coef_scaled=None, stream=None):
     """adct_encode_blocks.  img: uint8 CUDA tensor (H, W) (row pitch = stride(0)).
-    Returns (coef_int or None, coef_scaled or None), each (n_blocks, r)."""
+    t: a transform name / id, or an 8x8 integer matrix with orthogonal rows
+    (ADCT_CUSTOM).  Returns (coef_int or None, coef_scaled or None), each
+    (n_blocks, r)."""
     import torch
     _need_cuda(img, torch.uint8, "img")
+    if img.dim() != 2 or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D image with unit column stride")
+    tid, mat = _matrix_arg(t)
     h, w = img.shape
     nb = n_blocks(h, w)
+    _need_out(coef_int, torch.int16, nb * r, "coef_int")
+    _need_out(coef_scaled, torch.float32, nb * r, "coef_scaled")
     if want_int and coef_int is None:
         coef_int = torch.empty((nb, r), dtype=torch.int16, device=img.device)
     if want_scaled and coef_scaled is None:
         coef_scaled = torch.empty((nb, r), dtype=torch.float32, device=img.device)
-    _check(lib().adct_encode_blocks(_ptr(img), h, w, img.stride(0), _tid(t), None, r, quant_step,
+    _check(lib().adct_encode_blocks(_ptr(img), h, w, img.stride(0), tid, _mref(mat), r, quant_step,
                                     _ptr(coef_int), _ptr(coef_scaled), _stream(stream)))
     return coef_int, coef_scaled
 
 
 def decode_blocks(coef_int, h: int, w: int, t, r: int, quant_step: int = 0, out=None,
                   coef_scaled=None, stream=None):
-    """adct_decode_blocks.  Returns the (H, W) uint8 reconstruction."""
+    """adct_decode_blocks from int16 levels (coef_int) or float32 B
+    (coef_scaled; no quantiser step).  t as in encode_blocks.  Returns the
+    (H, W) uint8 reconstruction."""
     import torch
-    dev = (coef_int if coef_int is not None else coef_scaled).device
+    tid, mat = _matrix_arg(t)
+    nb = n_blocks(h, w)
+    _need_out(coef_int, torch.int16, nb * r, "coef_int")
+    _need_out(coef_scaled, torch.float32, nb * r, "coef_scaled")
+    src = coef_int if coef_int is not None else coef_scaled
+    if src is None:
+        raise ValueError("coef_int or coef_scaled is required")
+    _need_image(out, h, w, "out")
     if out is None:
-        out = torch.empty((h, w), dtype=torch.uint8, device=dev)
+        out = torch.empty((h, w), dtype=torch.uint8, device=src.device)
     _check(lib().adct_decode_blocks(_ptr(coef_int), _ptr(coef_scaled), h, w, _ptr(out),
-                                    out.stride(0), _tid(t), None, r, quant_step, _stream(stream)))
+                                    out.stride(0), tid, _mref(mat), r, quant_step, _stream(stream)))
     return out
 
 
@@ -232,14 +298,21 @@ class Evaluation:
 
 def evaluate_coding(img, t, r: int, quant_step: int = 0, coef_int=None, recon=None,
                     sse=None, stream=None) -> Evaluation:
-    """adct_evaluate_coding (synchronises the stream to return MSE / PSNR)."""
+    """adct_evaluate_coding (synchronises the stream to return MSE / PSNR).
+    t as in encode_blocks."""
     import torch
     _need_cuda(img, torch.uint8, "img")
+    if img.dim() != 2 or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D image with unit column stride")
+    tid, mat = _matrix_arg(t)
     h, w = img.shape
+    _need_out(coef_int, torch.int16, n_blocks(h, w) * r, "coef_int")
+    _need_image(recon, h, w, "recon")
+    _need_out(sse, torch.int64, 1, "sse")
     if sse is None:
         sse = torch.empty(1, dtype=torch.int64, device=img.device)
     mse, psnr = ctypes.c_double(), ctypes.c_double()
-    _check(lib().adct_evaluate_coding(_ptr(img), h, w, img.stride(0), _tid(t), None, r, quant_step,
+    _check(lib().adct_evaluate_coding(_ptr(img), h, w, img.stride(0), tid, _mref(mat), r, quant_step,
                                       _ptr(coef_int), _ptr(recon),
                                       recon.stride(0) if recon is not None else 0,
                                       _ptr(sse), ctypes.byref(mse), ctypes.byref(psnr),
@@ -261,20 +334,19 @@ def evaluate_stream(frames, planes, t, r: int, quant_step: int = 0, coef=None, r
     (n_frames, n_planes) int64 (uint64 values); does not synchronise."""
     import torch
     _need_cuda(frames, torch.uint8, "frames")
+    tid, mat = _matrix_arg(t)
     nf = frames.shape[0]
     _check_frames("frames", frames, planes, nf)
     if recon is not None:
         _need_cuda(recon, torch.uint8, "recon")
         _check_frames("recon", recon, planes, nf)
-    if coef is not None and coef.numel() < nf * stream_blocks_per_frame(planes) * r:
-        raise ValueError("coef needs n_frames * blocks * r entries")
+    _need_out(coef, torch.int16, nf * stream_blocks_per_frame(planes) * r, "coef")
+    _need_out(sse, torch.int64, nf * len(planes), "sse")
     if sse is None:
         sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
-    elif sse.numel() < nf * len(planes):
-        raise ValueError("sse is too small")
     arr = planes_struct(planes)
-    _check(lib().adct_evaluate_stream(_ptr(frames), frames.stride(0), nf, arr, len(planes), _tid(t),
-                                      None, r, quant_step, _ptr(coef), _ptr(recon),
+    _check(lib().adct_evaluate_stream(_ptr(frames), frames.stride(0), nf, arr, len(planes), tid,
+                                      _mref(mat), r, quant_step, _ptr(coef), _ptr(recon),
                                       recon.stride(0) if recon is not None else 0,
                                       _ptr(sse), _stream(stream)))
     return sse
@@ -300,6 +372,7 @@ def ssim(ref, test, planes, out=None, stream=None):
         _check_frames("test", test, planes, nf)
     if test.shape[0] != ref.shape[0]:
         raise ValueError("ref and test need the same number of frames")
+    _need_out(out, torch.float64, nf * len(planes), "out")
     if out is None:
         out = torch.empty((nf, len(planes)), dtype=torch.float64, device=ref.device)
     arr = planes_struct(planes)
@@ -333,14 +406,10 @@ def jam_evaluate_stream(frames, planes, n: int, r: int, quant_step: int = 0, coe
     # every byte the kernel touches must lie inside the tensors
     _check_frames("frames", frames, planes, nf)
     _check_frames("recon", recon, planes, nf)
+    _need_out(sse, torch.int64, nf * len(planes), "sse")
     if sse is None:
         sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
-    elif sse.numel() < nf * len(planes):
-        raise ValueError("sse is too small")
-    if coef is not None:
-        _need_cuda(coef, torch.int32, "coef")
-        if not coef.is_contiguous() or coef.numel() < nf * jam_blocks_per_frame(planes, n) * r:
-            raise ValueError("coef must be contiguous with n_frames * blocks * r entries")
+    _need_out(coef, torch.int32, nf * jam_blocks_per_frame(planes, n) * r, "coef")
     if recon is not None:
         _need_cuda(recon, torch.uint8, "recon")
     arr = planes_struct(planes)
@@ -364,6 +433,7 @@ def evaluate_inverse(frames, planes, T, r: int, recon=None, sse=None, stream=Non
     if recon is not None:
         _need_cuda(recon, torch.uint8, "recon")
     t = np.ascontiguousarray(np.asarray(T, dtype=np.int8).reshape(64))
+    _need_out(sse, torch.int64, nf * len(planes), "sse")
     if sse is None:
         sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device)
     arr = planes_struct(planes)
@@ -459,7 +529,9 @@ def evaluate_batch(base, images, transforms, r_lo: int = 1, r_hi: int = 63, sse=
     (n_images, n_transforms, r_hi - r_lo + 1) int64 (uint64 values)."""
     import torch
     _need_cuda(base, torch.uint8, "base")
+    _check_buffer("base", base, images)
     n = len(images)
+    _need_out(sse, torch.int64, n * len(transforms) * max(r_hi - r_lo + 1, 0), "sse")
     if sse is None:
         sse = torch.empty((n, len(transforms), r_hi - r_lo + 1), dtype=torch.int64, device=base.device)
     tids = _tid_array(transforms)
@@ -476,14 +548,16 @@ class BatchPlan:
     def __init__(self, base, images, transforms, r_lo: int = 1, r_hi: int = 63, sse=None,
                  autotune: bool = True, stream=None):
         import torch
+        self._h = _P()
         _need_cuda(base, torch.uint8, "base")
-        self.base = base
+        _check_buffer("base", base, images)
         n = len(images)
+        _need_out(sse, torch.int64, n * len(transforms) * max(r_hi - r_lo + 1, 0), "sse")
+        self.base = base
         self.sse = sse if sse is not None else torch.empty(
             (n, len(transforms), r_hi - r_lo + 1), dtype=torch.int64, device=base.device)
         self._planes = planes_struct(images)
         self._tids = _tid_array(transforms)
-        self._h = _P()
         _check(lib().adct_batch_plan_create(_ptr(base), self._planes, n, ctypes.cast(self._tids, _P),
                                             len(transforms), r_lo, r_hi, _ptr(self.sse),
                                             1 if autotune else 0, ctypes.byref(self._h),
@@ -543,7 +617,9 @@ def filter_grad(params, recon, orig, workspace=None, want_y: bool = False, strea
     n, h, w = recon.shape
     if orig.shape != recon.shape or not recon.is_contiguous() or not orig.is_contiguous():
         raise ValueError("recon and orig must be contiguous tensors of one shape")
-    if workspace is None:
+    if workspace is not None:
+        _need_out(workspace, torch.uint8, lib().adct_filter_workspace_bytes(n, h, w), "workspace")
+    else:
         workspace = filter_workspace(n, h, w, recon.device)
     grad = torch.empty(FILTER_PARAMS, dtype=torch.float32, device=recon.device)
     loss = torch.empty(1, dtype=torch.float32, device=recon.device)
@@ -646,10 +722,13 @@ def filter_apply(packed, frames, planes, out=None, orig=None, stream=None):
     Returns (out, sse) -- sse (n_frames, n_planes) int64 when orig is given."""
     import torch
     _need_cuda(frames, torch.uint8, "frames")
+    _need_out(packed, torch.uint8, lib().adct_filter_packed_bytes(), "packed")
     nf = frames.shape[0]
     if out is None:
         out = torch.zeros_like(frames)
     for name, buf in (("frames", frames), ("out", out), ("orig", orig)):
+        if buf is not None:
+            _need_cuda(buf, torch.uint8, name)
         _check_frames(name, buf, planes, nf)
     sse = torch.empty((nf, len(planes)), dtype=torch.int64, device=frames.device) if orig is not None else None
     arr = planes_struct(planes)
@@ -663,9 +742,16 @@ def filter_select(sse_filtered, sse_reference, plain, planes, out, keep=None, st
     """adct_filter_select: frames whose filtered SSE exceeds the reference's get
     the plain reconstruction copied into out.  Returns the keep flags (uint8)."""
     import torch
+    _need_cuda(plain, torch.uint8, "plain")
+    _need_cuda(out, torch.uint8, "out")
     nf = plain.shape[0]
     _check_frames("plain", plain, planes, nf)
     _check_frames("out", out, planes, nf)
+    _need_out(sse_filtered, torch.int64, nf * len(planes), "sse_filtered")
+    _need_out(sse_reference, torch.int64, nf * len(planes), "sse_reference")
+    if sse_filtered is None or sse_reference is None:
+        raise ValueError("sse_filtered and sse_reference are required")
+    _need_out(keep, torch.uint8, nf, "keep")
     if keep is None:
         keep = torch.empty(nf, dtype=torch.uint8, device=plain.device)
     arr = planes_struct(planes)

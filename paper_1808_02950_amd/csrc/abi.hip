@@ -82,55 +82,150 @@ int64_t lcm64(int64_t a, int64_t b) {
 }
 
 // Exact bound of the inverse numerator T^T (Y' o c c^T) T over 8-bit blocks for
-// the zig-zag prefix of length r.
+// the zig-zag prefix of length r, c_k = lcm(n) / n_k; saturates at INT64_MAX
+// (a caller's matrix can have a large lcm).
 int64_t inv_bound(const adct_matrix &m, int r) {
-    int64_t l1 = 1;
-    for (int k = 0; k < 8; ++k) l1 = lcm64(l1, m.n[k]);
-    int64_t c[8];
+    __int128 l1 = 1;
+    for (int k = 0; k < 8; ++k) {
+        __int128 x = l1, y = m.n[k];
+        while (y) { const __int128 t = x % y; x = y; y = t; }
+        l1 = l1 / x * m.n[k];
+        if (l1 > (__int128(1) << 62)) return INT64_MAX;
+    }
+    __int128 c[8];
     for (int k = 0; k < 8; ++k) c[k] = l1 / m.n[k];
-    int64_t best = 0;
+    const __int128 cap = __int128(INT64_MAX);
+    __int128 best = 0;
     for (int x = 0; x < 8; ++x)
         for (int y = 0; y < 8; ++y) {
-            int64_t kern[64] = {0};
+            __int128 kern[64] = {0};
             for (int z = 0; z < r; ++z) {
                 const int k = kZZ[z] >> 3, l = kZZ[z] & 7;
-                const int64_t w = c[k] * c[l] * m.T[8 * k + x] * m.T[8 * l + y];
+                const __int128 w = c[k] * c[l] * m.T[8 * k + x] * m.T[8 * l + y];
                 if (!w) continue;
+                if (w > cap || -w > cap) return INT64_MAX;
                 for (int u = 0; u < 8; ++u)
                     for (int v = 0; v < 8; ++v) kern[8 * u + v] += w * m.T[8 * k + u] * m.T[8 * l + v];
             }
-            int64_t pos = 0, neg = 0;
+            __int128 pos = 0, neg = 0;
             for (int i = 0; i < 64; ++i) {
                 if (kern[i] > 0) pos += kern[i]; else neg -= kern[i];
             }
             best = std::max(best, 255 * std::max(pos, neg));
+            if (best > cap) return INT64_MAX;
         }
-    return best;
+    return int64_t(best);
+}
+
+// A caller's matrix: n must be diag(T T^T), every row non-zero, rows orthogonal.
+adct_status check_custom(const adct_matrix *c) {
+    if (!c) return fail(ADCT_EINVAL, "ADCT_CUSTOM needs a matrix in `custom`");
+    for (int k = 0; k < 8; ++k) {
+        for (int l = 0; l < 8; ++l) {
+            int64_t d = 0;
+            for (int j = 0; j < 8; ++j) d += int64_t(c->T[8 * k + j]) * c->T[8 * l + j];
+            if (k == l && (d == 0 || d != c->n[k]))
+                return fail(ADCT_EINVAL, "custom matrix: n[k] must equal (T T^T)_kk > 0");
+            if (k != l && d != 0)
+                return fail(ADCT_EINVAL, "custom matrix: rows are not orthogonal (T T^T not diagonal); "
+                                         "the transpose decoder of Sec. 6.1.1 needs orthogonal rows");
+        }
+    }
+    return ADCT_OK;
+}
+
+// Run-time kernel constants of matrix m (all entries wave-uniform).
+adct_status build_rt(const adct_matrix &m, RtMatArgs *rt) {
+    int64_t l1 = 1;
+    for (int k = 0; k < 8; ++k) {
+        l1 = lcm64(l1, m.n[k]);
+        if (l1 > (int64_t(1) << 26)) return fail(ADCT_EOVERFLOW, "lcm of the row norms exceeds 2^26");
+    }
+    memset(rt, 0, sizeof(*rt));
+    rt->L = l1 * l1;
+    if (rt->L >= kRtMaxL) return fail(ADCT_EOVERFLOW, "exact inverse denominator exceeds 2^53");
+    rt->inv_2L = 1.0 / double(2 * rt->L);
+    for (int k = 0; k < 8; ++k)
+        for (int l = 0; l < 8; ++l) {
+            const int i = 8 * k + l;
+            rt->t[i] = m.T[i];
+            const int64_t v = int64_t(m.n[k]) * m.n[l];
+            const int64_t mu = int64_t(llround(sqrt(double(v))));
+            rt->mu[i] = (mu * mu == v) ? int32_t(mu) : 0;
+            rt->inv_2mu[i] = rt->mu[i] ? float(0.5 / double(rt->mu[i])) : 0.f;
+            rt->ckl[i] = (l1 / m.n[k]) * (l1 / m.n[l]);
+            rt->skl[i] = inv_sqrt_newton(v);
+        }
+    return ADCT_OK;
+}
+
+// The run-time exact inverse sums int64 terms T[k][x] c_k c_l C_kl into U[x][l],
+// then T[l][y] U[x][l] into the numerator; with |C| <= cmax (the forward bound,
+// or any int16 a decoder is handed) every partial sum must stay below 2^61,
+// and the denominator L below 2^53.
+bool rt_words_fit(const adct_matrix &m, int64_t cmax) {
+    __int128 l1 = 1;
+    for (int k = 0; k < 8; ++k) {
+        __int128 x = l1, y = m.n[k];
+        while (y) { const __int128 t = x % y; x = y; y = t; }
+        l1 = l1 / x * m.n[k];
+        if (l1 > (__int128(1) << 26)) return false;
+    }
+    if (l1 * l1 >= kRtMaxL) return false;
+    __int128 umax = 0;
+    for (int x = 0; x < 8; ++x)
+        for (int l = 0; l < 8; ++l) {
+            __int128 u = 0;
+            for (int k = 0; k < 8; ++k)
+                u += __int128(m.T[8 * k + x] < 0 ? -m.T[8 * k + x] : m.T[8 * k + x]) *
+                     (l1 / m.n[k]) * (l1 / m.n[l]) * cmax;
+            umax = std::max(umax, u);
+        }
+    __int128 nmax = 0;
+    for (int y = 0; y < 8; ++y) {
+        __int128 v = 0;
+        for (int l = 0; l < 8; ++l) v += __int128(m.T[8 * l + y] < 0 ? -m.T[8 * l + y] : m.T[8 * l + y]) * umax;
+        nmax = std::max(nmax, v);
+    }
+    return nmax < kRtMaxInvNum;
 }
 
 struct Prepared {
     adct_matrix m;
     int band;
     bool quant;
+    bool runtime;      // the matrix goes to the run-time kernels (ADCT_CUSTOM)
+    RtMatArgs rt;
 };
 
 adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int quant_step,
                     bool need_int16_coef, Prepared *out, CodecArgs *a) {
     if (t == ADCT_DCT) return fail(ADCT_ENOTSUP, "the exact DCT runs through the MFMA comparator path");
-    if (t == ADCT_CUSTOM) return fail(ADCT_ENOTSUP, "custom matrices are not supported by the fused codec");
-    if (!is_builtin_int(t)) return fail(ADCT_EINVAL, "unknown transform id");
+    if (t != ADCT_CUSTOM && !is_builtin_int(t)) return fail(ADCT_EINVAL, "unknown transform id");
     if (r < 1 || r > 64) return fail(ADCT_ERANGE, "r must be in [1, 64]");
     if (quant_step < 0 || quant_step > 65535) return fail(ADCT_ERANGE, "quant_step must be in [0, 65535]");
-    (void)custom;
-    matrix_of(t, &out->m);
+    out->runtime = (t == ADCT_CUSTOM);
+    if (out->runtime) {
+        adct_status st = check_custom(custom);
+        if (st) return st;
+        out->m = *custom;
+    } else {
+        matrix_of(t, &out->m);
+    }
     out->band = r <= 10 ? 3 : 14;
     out->quant = quant_step > 0;
     const int64_t fb = fwd_bound(out->m);
     if (!out->quant) {
         if (need_int16_coef && fb > 32767)
             return fail(ADCT_EOVERFLOW, "the integer stage of this transform exceeds int16; request coef_scaled");
-        if (2 * inv_bound(out->m, r) + (int64_t(1) << 22) >= (int64_t(1) << 31))
+        if (out->runtime) {
+            if (!rt_words_fit(out->m, std::max<int64_t>(fb, 32767)))
+                return fail(ADCT_EOVERFLOW, "exact inverse of this matrix exceeds 64-bit words");
+        } else if (2 * inv_bound(out->m, r) + (int64_t(1) << 22) >= (int64_t(1) << 31)) {
             return fail(ADCT_EOVERFLOW, "inverse numerator exceeds int32");
+        }
+    } else if (out->runtime && fb >= kRtMaxQuantY) {
+        return fail(ADCT_ERANGE, "custom matrix: |Y| bound too large for the float64 quantiser (>= 2^24)");
     }
     const int32_t *n = out->m.n;
     if (out->quant) {
@@ -162,6 +257,10 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
                     return fail(ADCT_ERANGE, "quant_step too large for the exact integer quantiser");
             }
         }
+    if (out->runtime) {
+        adct_status st = build_rt(out->m, &out->rt);
+        if (st) return st;
+    }
     a->step = quant_step;
     a->inv_step_f = quant_step ? float(1.0 / quant_step) : 0.f;
     a->inv_step_d = quant_step ? 1.0 / quant_step : 0.0;
@@ -310,6 +409,7 @@ static adct_status stream_impl(const uint8_t *frames, int64_t frame_stride, int 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     st = zero_u64(sse, int64_t(n_frames) * n_planes, s);
     if (st) return st;
+    if (pr.runtime) return launch_codec_rt(pr.band, pr.quant, false, kEvaluate, a, pr.rt, wpf * n_frames, s);
     return launch_codec(t, pr.band, pr.quant, kEvaluate, a, wpf * n_frames, s);
 }
 
@@ -397,7 +497,9 @@ adct_status adct_encode_blocks(const uint8_t *img, int H, int W, int pitch,
     a.coef_f = coef_scaled;
     a.n_frames = 1;
     a.r = r;
-    return launch_codec(t, pr.band, pr.quant, kEncode, a, waves, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (pr.runtime) return launch_codec_rt(pr.band, pr.quant, false, kEncode, a, pr.rt, waves, hs);
+    return launch_codec(t, pr.band, pr.quant, kEncode, a, waves, hs);
 }
 
 adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled,
@@ -428,20 +530,37 @@ adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled
         d.n_frames = 1;
         return launch_dct(kDecode, d, waves, reinterpret_cast<hipStream_t>(stream));
     }
-    if (coef_scaled) return fail(ADCT_ENOTSUP, "float coefficients decode through the exact-DCT path");
-    if (!aligned(coef_int, 4)) return fail(ADCT_EDIM, "coef_int must be 4-byte aligned");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (!aligned(coef_int ? (const void *)coef_int : (const void *)coef_scaled, 4))
+        return fail(ADCT_EDIM, "coefficients must be 4-byte aligned");
     CodecArgs a;
     memset(&a, 0, sizeof(a));
     Prepared pr;
+    adct_plane pl = {0, H, W, pitch_out, 0};
+    if (coef_scaled) {
+        // float B: A = C_hat^T B' C_hat in float64 with the run-time kernel
+        if (quant_step != 0)
+            return fail(ADCT_EINVAL, "float coefficients are decoded without a quantiser step");
+        st = prepare(t, custom, r, 0, false, &pr, &a);
+        if (st) return st;
+        st = build_rt(pr.m, &pr.rt);
+        if (st) return st;
+        const int waves = setup_planes(&a, &pl, 1);
+        a.out = out;
+        a.coef_f = const_cast<float *>(coef_scaled);
+        a.n_frames = 1;
+        a.r = r;
+        return launch_codec_rt(pr.band, false, true, kDecode, a, pr.rt, waves, hs);
+    }
     st = prepare(t, custom, r, quant_step, true, &pr, &a);
     if (st) return st;
-    adct_plane pl = {0, H, W, pitch_out, 0};
     const int waves = setup_planes(&a, &pl, 1);
     a.out = out;
     a.coef = const_cast<int16_t *>(coef_int);
     a.n_frames = 1;
     a.r = r;
-    return launch_codec(t, pr.band, pr.quant, kDecode, a, waves, reinterpret_cast<hipStream_t>(stream));
+    if (pr.runtime) return launch_codec_rt(pr.band, pr.quant, false, kDecode, a, pr.rt, waves, hs);
+    return launch_codec(t, pr.band, pr.quant, kDecode, a, waves, hs);
 }
 
 adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, int n_frames,

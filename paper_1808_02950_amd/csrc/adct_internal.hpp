@@ -111,6 +111,15 @@ constexpr ZZInv make_zz_inv() {
 constexpr ZZInv kZZInv = make_zz_inv();
 constexpr int zz_pos(int k, int l) { return kZZInv.pos[8 * k + l]; }
 
+// 1/sqrt(v) in float64 from Newton's iteration for sqrt(v): the same value in
+// the compile-time tables of the built-in matrices and in the run-time tables
+// the host builds for a caller's matrix.
+constexpr double inv_sqrt_newton(int64_t v) {
+    double r = double(v);
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + double(v) / r);
+    return 1.0 / r;
+}
+
 // Per-transform constants derived at compile time.
 template <int ID>
 struct Tf {
@@ -151,9 +160,7 @@ struct Tf {
                 for (int32_t c = 1; c * c <= v; ++c)
                     if (c * c == v) m = c;
                 t.mu[8 * k + l] = m;
-                double r = double(v);               // Newton iteration for sqrt(v)
-                for (int i = 0; i < 64; ++i) r = 0.5 * (r + double(v) / r);
-                t.skl[8 * k + l] = 1.0 / r;
+                t.skl[8 * k + l] = inv_sqrt_newton(v);
             }
         return t;
     }
@@ -228,6 +235,27 @@ struct DctArgs {
 };
 
 enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2 };
+
+// Constants of an integer matrix given at run time (ADCT_CUSTOM, and the
+// float-coefficient decode of the built-in matrices), a second kernel argument
+// of the run-time codec kernels.  All entries are wave-uniform.
+struct RtMatArgs {
+    int32_t t[64];       // T[k][m] at 8k + m
+    int32_t mu[64];      // mu with mu^2 = n_k n_l, 0 when n_k n_l is not a square
+    float inv_2mu[64];   // 0.5 / mu (rational classes)
+    int64_t ckl[64];     // c_k c_l with c_k = L1 / n_k, L1 = lcm(n): exact inverse weights
+    double skl[64];      // s_k s_l = 1 / sqrt(n_k n_l)
+    int64_t L;           // L1^2, the exact inverse's denominator
+    double inv_2L;       // 1 / (2 L)
+};
+
+// Word sizes the run-time kernels assume (checked on the host before launch).
+constexpr int64_t kRtMaxL = int64_t(1) << 53;       // L, so 511 L < 2^63
+constexpr int64_t kRtMaxInvNum = int64_t(1) << 61;  // |exact inverse numerator|
+constexpr int64_t kRtMaxQuantY = int64_t(1) << 24;  // |Y| with a quantiser
+
+adct_status launch_codec_rt(int band, bool quant, bool float_in, Mode mode, const CodecArgs &a,
+                            const RtMatArgs &m, int total_waves, hipStream_t s);
 
 adct_status launch_dct(Mode mode, const DctArgs &a, int total_waves, hipStream_t s);
 

@@ -7,12 +7,10 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "adct_internal.hpp"
+#include "codec_tile.hpp"
 
 namespace adct {
 namespace {
-
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ 1-D passes
 
@@ -131,45 +129,6 @@ __device__ __forceinline__ int rne_div_clip(int n) {
     return int(q) - int(tie & (q & 1u));
 }
 
-__device__ __forceinline__ int byte_of(uint32_t w, int i) { return int((w >> (8 * i)) & 0xffu); }
-
-// round-half-to-even of a float64 to int32 (|x| < 2^31): adding 1.5 * 2^52
-// leaves the rounded integer in the low word of the sum.
-__device__ __forceinline__ int rne_i32(double x) {
-    return __double2loint(x + 6755399441055744.0);
-}
-
-__device__ __forceinline__ int clamp255(int v) { return min(max(v, 0), 255); }
-
-// round-half-away(Y / d), d = step * mu, for the classes where n_k n_l = mu^2
-// (Y / d can be an exact half): floor((2|Y| + d) / (2d)) from a float estimate
-// corrected in exact integer arithmetic (2|Y| + d < 2^24 is checked on the host).
-__device__ __forceinline__ int quant_rational(int y, int step, int mu, float inv_2mu, float inv_step) {
-    const int ay = y < 0 ? -y : y;
-    const int d = step * mu;                                  // wave-uniform
-    const int d2 = d + d;
-    const int num = 2 * ay + d;
-    int q = int(float(num) * inv_2mu * inv_step);
-    const int rem = num - __mul24(q, d2);
-    q += (rem >= d2) ? 1 : 0;
-    q -= (rem < 0) ? 1 : 0;
-    return y < 0 ? -q : q;
-}
-
-// round-half-away(Y s_k s_l / step) where s_k s_l = 1/sqrt(n_k n_l) is
-// irrational: the quotient is never an exact half (its nearest half is > 1e-9
-// away for |Y| < 2^16, far above the float64 error), so round-half-to-even of
-// the float64 product gives the same integer.
-__device__ __forceinline__ int quant_irrational(int y, double skl, double inv_step) {
-    return rne_i32(double(y) * skl * inv_step);
-}
-
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // ------------------------------------------------------------------ kernel
 //
 // BAND: only coefficients (k, l) with k + l <= BAND can be retained (r <= 10
@@ -179,78 +138,6 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v) {
 // The grid is persistent: each wave walks tiles gw, gw + stride, ... (a tile is
 // 64 consecutive blocks of one plane of one frame) and issues the loads of its
 // next tile before it transforms the current one.
-
-struct Tile {
-    int f, p;            // frame, plane (wave-uniform)
-    int b;               // block index inside the plane (per lane)
-    bool active;
-    uint32_t in_off, out_off;
-};
-
-__device__ __forceinline__ Tile tile_of(const CodecArgs &a, int gw, int lane) {
-    Tile t;
-    t.f = gw / a.waves_per_frame;
-    const int w = gw - t.f * a.waves_per_frame;
-    int p = 0;
-    while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
-    t.p = p;
-    const PlaneArg &P = a.pl[p];
-    const int b0 = (w - P.wave_start) * 64;             // first block of the wave
-    const int by0 = b0 / P.nbx;
-    const int bx0 = b0 - by0 * P.nbx;
-    t.b = b0 + lane;
-    t.active = t.b < P.nblocks;
-    int by, bx;
-    if (P.nbx >= 64) {                                   // at most one row change
-        bx = bx0 + lane;
-        by = by0;
-        if (bx >= P.nbx) {
-            bx -= P.nbx;
-            ++by;
-        }
-    } else {
-        by = t.b / P.nbx;
-        bx = t.b - by * P.nbx;
-    }
-    if (!t.active) by = bx = 0;
-    t.in_off = __umul24(uint32_t(8 * by), uint32_t(P.pitch_in)) + uint32_t(8 * bx);
-    t.out_off = __umul24(uint32_t(8 * by), uint32_t(P.pitch_out)) + uint32_t(8 * bx);
-    return t;
-}
-
-__device__ __forceinline__ void load_tile(const CodecArgs &a, const Tile &t, uint32_t (&pix)[8][2]) {
-    const PlaneArg &P = a.pl[t.p];
-    const uint8_t *src = a.in + int64_t(t.f) * a.fs_in + P.in_off + t.in_off;
-    // inactive lanes point at block (0, 0) of the plane: the load stays in
-    // bounds and its result is never stored or scored
-#pragma unroll
-    for (int x = 0; x < 8; ++x) {
-        const u32x2 v = __builtin_nontemporal_load((const u32x2 *)(src + x * P.pitch_in));
-        pix[x][0] = v.x;
-        pix[x][1] = v.y;
-    }
-}
-
-// Pack a reconstructed row (q in [0, 255]) into bytes and accumulate the two
-// dot-product sums whose combination is the squared error:
-// sum (q - a)^2 = [sum q^2 + sum a^2] - 2 sum q a.
-__device__ __forceinline__ u32x2 emit_row(const int (&q)[8], uint32_t w0, uint32_t w1,
-                                          uint32_t &sq, uint32_t &cross) {
-    const uint32_t r01 = uint32_t(q[0]) | (uint32_t(q[1]) << 16);
-    const uint32_t r23 = uint32_t(q[2]) | (uint32_t(q[3]) << 16);
-    const uint32_t r45 = uint32_t(q[4]) | (uint32_t(q[5]) << 16);
-    const uint32_t r67 = uint32_t(q[6]) | (uint32_t(q[7]) << 16);
-    u32x2 out;
-    out.x = __builtin_amdgcn_perm(r23, r01, 0x06040200u);
-    out.y = __builtin_amdgcn_perm(r67, r45, 0x06040200u);
-    sq = __builtin_amdgcn_udot4(out.x, out.x, sq, false);
-    sq = __builtin_amdgcn_udot4(out.y, out.y, sq, false);
-    sq = __builtin_amdgcn_udot4(w0, w0, sq, false);
-    sq = __builtin_amdgcn_udot4(w1, w1, sq, false);
-    cross = __builtin_amdgcn_udot4(out.x, w0, cross, false);
-    cross = __builtin_amdgcn_udot4(out.y, w1, cross, false);
-    return out;
-}
 
 template <int ID, int BAND, bool QUANT, int MODE>
 __device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
@@ -480,26 +367,6 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
     }
 }
 
-// Persistent grid: as many 4-wave workgroups as the device keeps resident
-// (occupancy x CUs), never more than there are tiles.
-template <class K>
-adct_status persistent_grid(K kernel, int total_waves, int *grid) {
-    static thread_local int cached_dev = -1, cus = 0;
-    int dev = 0;
-    ADCT_HIP(hipGetDevice(&dev));
-    if (dev != cached_dev) {
-        ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        cached_dev = dev;
-    }
-    int per_cu = 0;
-    ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
-    if (per_cu < 1) per_cu = 1;
-    const int knob = codec_wgs_per_cu();
-    if (knob > 0) per_cu = std::min(per_cu, knob);
-    const int64_t want = (int64_t(total_waves) + 3) / 4;
-    *grid = knob < 0 ? int(want) : int(std::min<int64_t>(want, int64_t(per_cu) * cus));
-    return ADCT_OK;
-}
 
 template <int ID, int BAND, bool QUANT, int M>
 adct_status launch_one(const CodecArgs &a, int total_waves, hipStream_t s) {

@@ -119,6 +119,46 @@ def test_tie_free_quantiser_steps_accepted():
     assert lib.adct_check_codec_args(A.LO, None, 10, 0, 0) == 0
 
 
+def test_custom_matrix_validation_host_only():
+    """ADCT_CUSTOM takes any int8 matrix with orthogonal rows: the caller's n must
+    be diag(T T^T); a missing matrix, non-orthogonal rows or a wrong n are
+    ADCT_EINVAL; the quantiser-step rule and the int16 bound apply as for the
+    built-in matrices."""
+    lib = A.lib()
+    m = A._matrix_struct(M.T1)
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 0, 1) == 0
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 16, 1) == 0
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 12, 1) == -7
+    assert lib.adct_check_codec_args(A.CUSTOM, None, 10, 0, 1) == -1
+    bad_n = A._matrix_struct(M.T1)
+    bad_n.n[2] += 1
+    assert lib.adct_check_codec_args(A.CUSTOM, bad_n, 10, 0, 1) == -1
+    skew = M.T1.copy()
+    skew[1, 0] += 1
+    assert lib.adct_check_codec_args(A.CUSTOM, A._matrix_struct(skew), 10, 0, 1) == -1
+    assert lib.adct_check_codec_args(A.CUSTOM, A._matrix_struct(M.t_sdct()), 10, 0, 1) == -1
+    zero_row = M.T1.copy()
+    zero_row[7] = 0
+    assert lib.adct_check_codec_args(A.CUSTOM, A._matrix_struct(zero_row), 10, 0, 1) == -1
+    lo = A._matrix_struct(M.T_LO_X2)
+    assert lib.adct_check_codec_args(A.CUSTOM, lo, 10, 0, 1) == -4      # int16 output
+    assert lib.adct_check_codec_args(A.CUSTOM, lo, 10, 0, 0) == 0
+    assert lib.adct_check_codec_args(A.CUSTOM, lo, 10, 32, 1) == 0
+    # entries up to +-127 with orthogonal rows: a scaled Hadamard-like matrix
+    big = np.array([[1, 1], [1, -1]])
+    h8 = np.kron(np.kron(big, big), big) * 127
+    assert lib.adct_check_codec_args(A.CUSTOM, A._matrix_struct(h8), 64, 0, 0) == 0
+    assert lib.adct_check_codec_args(A.CUSTOM, A._matrix_struct(h8), 64, 16, 0) == -3   # |Y| >= 2^24
+
+
+def test_decode_float_coefficients_host_only():
+    lib = A.lib()
+    # exactly one of coef_int / coef_scaled; float B takes no quantiser step
+    assert lib.adct_decode_blocks(FAKE, FAKE, 8, 8, FAKE, 8, A.T1, None, 10, 0, None) == -1
+    assert lib.adct_decode_blocks(None, FAKE, 8, 8, FAKE, 8, A.T1, None, 10, 16, None) == -1
+    assert lib.adct_decode_blocks(None, FAKE, 8, 8, FAKE, 8, A.CUSTOM, None, 10, 0, None) == -1
+
+
 def test_search_argument_errors_host_only():
     lib = A.lib()
     n = ctypes.c_int()
