@@ -283,6 +283,18 @@ adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t frame_stride, i
 adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, const double *rho, int n_rho,
                                    double *cg_out, adct_stream_t stream);
 
+/* The same sweep for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, tight serving loops): identical arguments and results,
+ * but the device copies of c_hat and rho and the results are staged in a fixed
+ * 2 MiB array that each GPU the library runs on holds from the first call until
+ * the process ends; no call allocates or frees anything.  Limit:
+ * 64 n_t + n_rho + n_t n_rho <= 262,144 (ADCT_ERANGE beyond).  Every call on
+ * one GPU stages into the same array: calls that overlap on one GPU (other
+ * threads, other streams) race and must be serialised by the caller; the call
+ * synchronises `stream` before it returns.  Other errors as above. */
+adct_status adct_coding_gain_sweep_noalloc(const double *c_hat, int n_t, const double *rho, int n_rho,
+                                           double *cg_out, adct_stream_t stream);
+
 /* ---------------------------------------------------------------- search */
 
 /* Search modes of adct_derive_transform (Sec. 3.5 and 4.1).  Exact ties in

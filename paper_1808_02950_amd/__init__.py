@@ -68,6 +68,7 @@ _SIGNATURES = {
     "adct_jam_matrix": (_I, [_I, _I, _P, _P]),
     "adct_evaluate_inverse": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _I, _P, _I64, _P, _P]),
     "adct_coding_gain_sweep": (_I, [_P, _I, _P, _I, _P, _P]),
+    "adct_coding_gain_sweep_noalloc": (_I, [_P, _I, _P, _I, _P, _P]),
     "adct_jam_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I, _I, _I, _I,
                                       _P, _P, _I64, _P, _P]),
     "adct_derive_transform": (_I, [_P, _I, _I, _P, _I, _I, ctypes.POINTER(Matrix), _I,
@@ -451,6 +452,17 @@ def coding_gain_sweep(c_hats, rhos, stream=None):
     out = np.zeros((c.shape[0], r.shape[0]), dtype=np.float64)
     _check(lib().adct_coding_gain_sweep(c.ctypes.data, c.shape[0], r.ctypes.data, r.shape[0],
                                         out.ctypes.data, _stream(stream)))
+    return out
+
+
+def coding_gain_sweep_noalloc(c_hats, rhos, stream=None):
+    """adct_coding_gain_sweep_noalloc: the same results without any device
+    allocation (fixed per-device staging; calls on one GPU must not overlap)."""
+    c = np.ascontiguousarray(np.asarray(c_hats, dtype=np.float64).reshape(-1, 64))
+    r = np.ascontiguousarray(np.asarray(rhos, dtype=np.float64).reshape(-1))
+    out = np.zeros((c.shape[0], r.shape[0]), dtype=np.float64)
+    _check(lib().adct_coding_gain_sweep_noalloc(c.ctypes.data, c.shape[0], r.ctypes.data, r.shape[0],
+                                                out.ctypes.data, _stream(stream)))
     return out
 
 

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "adct_internal.hpp"
@@ -369,4 +370,64 @@ extern "C" adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, cons
     if (dr) (void)hipFree(dr);
     if (dout) (void)hipFree(dout);
     return st;
+}
+
+// ---------------------------------------------------------------- no-allocation form
+//
+// The same sweep for callers that cannot allocate device memory: the staged
+// matrices, correlations and results live in one file-scope device array of a
+// fixed size, held by each GPU the library runs on until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: every
+// host use goes through the device address that hipGetSymbolAddress returns,
+// taken once per device with that device current.
+
+namespace {
+
+constexpr int64_t kCgScratchDoubles = int64_t(1) << 18;   // 2 MiB per device
+static __device__ __align__(256) double scratch[kCgScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+adct_status scratch_of_current_device(double **out) {
+    int dev = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ADCT_EDEVICE, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        ADCT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(ADCT_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ADCT_OK;
+}
+
+}  // namespace
+
+extern "C" adct_status adct_coding_gain_sweep_noalloc(const double *c_hat, int n_t, const double *rho,
+                                                      int n_rho, double *cg_out, adct_stream_t stream) {
+    if (!c_hat || !rho || !cg_out) return fail(ADCT_EINVAL, "c_hat, rho and cg_out are required");
+    if (n_t < 1 || n_rho < 1) return fail(ADCT_ERANGE, "n_t and n_rho must be >= 1");
+    const int64_t nc = int64_t(n_t) * 64, no = int64_t(n_t) * n_rho;
+    if (nc + n_rho + no > kCgScratchDoubles)
+        return fail(ADCT_ERANGE, "64 n_t + n_rho + n_t n_rho must not exceed 262,144 doubles "
+                                 "(the fixed scratch of the no-allocation sweep)");
+    for (int j = 0; j < n_rho; ++j)
+        if (!(rho[j] >= 0.0 && rho[j] < 1.0)) return fail(ADCT_ERANGE, "rho must be in [0, 1)");
+    double *base = nullptr;
+    adct_status st = scratch_of_current_device(&base);
+    if (st) return st;
+    double *dc = base, *dr = base + nc, *dout = base + nc + n_rho;   // every entry written before use
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ADCT_HIP(hipMemcpyAsync(dc, c_hat, size_t(nc) * sizeof(double), hipMemcpyHostToDevice, hs));
+    ADCT_HIP(hipMemcpyAsync(dr, rho, size_t(n_rho) * sizeof(double), hipMemcpyHostToDevice, hs));
+    hipLaunchKernelGGL(k_coding_gain, dim3(unsigned((no + 255) / 256)), dim3(256), 0, hs, dc, n_t, dr, n_rho,
+                       dout);
+    ADCT_HIP(hipGetLastError());
+    ADCT_HIP(hipMemcpyAsync(cg_out, dout, size_t(no) * sizeof(double), hipMemcpyDeviceToHost, hs));
+    ADCT_HIP(hipStreamSynchronize(hs));
+    return ADCT_OK;
 }
