@@ -210,6 +210,18 @@ adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, in
                                  int16_t *coef, uint8_t *recon, int64_t frame_stride_out,
                                  uint64_t *sse, adct_stream_t stream);
 
+/* Measurement helper, not a step of the method: the loads and stores of
+ * adct_evaluate_stream for the same arguments (every block read once, the
+ * first r int16 coefficients and the reconstruction written, with the same
+ * tiles, access widths and persistent grid) and none of its arithmetic: recon
+ * receives the input pixels and coef receives bytes of them.  Its duration is
+ * the achievable HBM rate of the codec's read / write mix on this device, the
+ * ceiling the codec's own rate is compared with.  coef and recon are nullable;
+ * errors as for adct_evaluate_stream. */
+adct_status adct_stream_bandwidth_probe(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                        const adct_plane *planes, int n_planes, int r, int16_t *coef,
+                                        uint8_t *recon, int64_t frame_stride_out, adct_stream_t stream);
+
 /* ---------------------------------------------------------------- 16 / 32 points */
 
 /* The N-point matrix (N = 16 or 32) that the Jridi-Alfalou-Meher construction

@@ -64,6 +64,7 @@ _SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_double), _P]),
     "adct_evaluate_stream": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I,
                                   ctypes.POINTER(Matrix), _I, _I, _P, _P, _I64, _P, _P]),
+    "adct_stream_bandwidth_probe": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _I, _P, _P, _I64, _P]),
     "adct_ssim": (_I, [_P, _I64, _P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _P]),
     "adct_jam_matrix": (_I, [_I, _I, _P, _P]),
     "adct_evaluate_inverse": (_I, [_P, _I64, _I, ctypes.POINTER(Plane), _I, _P, _I, _P, _I64, _P, _P]),
@@ -351,6 +352,22 @@ def evaluate_stream(frames, planes, t, r: int, quant_step: int = 0, coef=None, r
                                       recon.stride(0) if recon is not None else 0,
                                       _ptr(sse), _stream(stream)))
     return sse
+
+
+def stream_bandwidth_probe(frames, planes, r: int, coef=None, recon=None, stream=None):
+    """adct_stream_bandwidth_probe: the loads and stores of evaluate_stream for
+    these arguments without the arithmetic (the HBM ceiling of that mix)."""
+    import torch
+    _need_cuda(frames, torch.uint8, "frames")
+    nf = frames.shape[0]
+    _check_frames("frames", frames, planes, nf)
+    if recon is not None:
+        _need_cuda(recon, torch.uint8, "recon")
+        _check_frames("recon", recon, planes, nf)
+    _need_out(coef, torch.int16, nf * stream_blocks_per_frame(planes) * r, "coef")
+    _check(lib().adct_stream_bandwidth_probe(_ptr(frames), frames.stride(0), nf, planes_struct(planes), len(planes),
+                                             r, _ptr(coef), _ptr(recon), recon.stride(0) if recon is not None else 0,
+                                             _stream(stream)))
 
 
 def ssim(ref, test, planes, out=None, stream=None):

@@ -196,6 +196,7 @@ struct Prepared {
     bool quant;
     bool runtime;      // the matrix goes to the run-time kernels (ADCT_CUSTOM)
     RtMatArgs rt;
+    QuantTables qt;    // built-in kernels' quantiser constants
 };
 
 adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int quant_step,
@@ -255,8 +256,25 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
                 const int64_t d2 = 2 * int64_t(quant_step) * mu;
                 if (2 * fb + d2 >= (int64_t(1) << 24) || d2 >= (int64_t(1) << 23))
                     return fail(ADCT_ERANGE, "quant_step too large for the exact integer quantiser");
+                // the built-in kernels' float32 form (quant_rational_f) needs |Y| + d < 2^20
+                if (!out->runtime && fb + d2 / 2 >= (int64_t(1) << 20))
+                    return fail(ADCT_ERANGE, "quant_step too large for the exact quantiser");
             }
         }
+    memset(&out->qt, 0, sizeof(out->qt));
+    if (out->quant) {
+        for (int z = 0; z < 64; ++z) {
+            const int k = kZZ[z] >> 3, l = kZZ[z] & 7;
+            const int64_t prod = int64_t(n[k]) * n[l];
+            const int64_t mu = int64_t(llround(sqrt(double(prod))));
+            const double skl = inv_sqrt_newton(prod);
+            const double d = double(quant_step) * double(mu);
+            out->qt.qc1[z] = (mu * mu == prod) ? float(1.0 / d) : 0.f;
+            out->qt.qc2[z] = (mu * mu == prod) ? float((d + 0.5) / (2.0 * d)) : 0.f;
+            out->qt.qinv[z] = skl / double(quant_step);
+            out->qt.qdeq[z] = double(quant_step) * skl;
+        }
+    }
     if (out->runtime) {
         adct_status st = build_rt(out->m, &out->rt);
         if (st) return st;
@@ -276,8 +294,9 @@ adct_status check_plane(const void *base, int64_t offset, int H, int W, int pitc
         return fail(ADCT_EDIM, std::string(what) + ": base, offsets and pitch must be 8-byte aligned");
     if (int64_t(H / 8) * (W / 8) > (int64_t(1) << 30))
         return fail(ADCT_EDIM, std::string(what) + ": too many blocks");
-    if (pitch >= (1 << 24) || int64_t(H) * pitch >= (int64_t(1) << 32))
-        return fail(ADCT_EDIM, std::string(what) + ": plane larger than 4 GiB or pitch >= 2^24");
+    if (pitch >= (1 << 24) || H >= (1 << 24) || int64_t(H) * pitch >= (int64_t(1) << 32))
+        return fail(ADCT_EDIM, std::string(what) + ": plane larger than 4 GiB, pitch >= 2^24 or H >= 2^24 "
+                                                   "(row offsets are formed with 24-bit multiplies)");
     return ADCT_OK;
 }
 
@@ -294,12 +313,14 @@ int setup_planes(CodecArgs *a, const adct_plane *pl, int np) {
         d.nblocks = (pl[p].H / 8) * (pl[p].W / 8);
         d.wave_start = waves;
         d.block_off = blocks;
+        magic_u31(uint32_t(d.nbx), &d.nbx_m, &d.nbx_s);
         waves += (d.nblocks + 63) / 64;
         blocks += d.nblocks;
     }
     a->n_planes = np;
     a->blocks_per_frame = blocks;
     a->waves_per_frame = waves;
+    magic_u31(uint32_t(waves), &a->wpf_m, &a->wpf_s);
     return waves;
 }
 
@@ -316,12 +337,14 @@ int setup_dct(DctArgs *a, const adct_plane *pl, int np, int r, int step) {
         d.nblocks = (pl[p].H / 8) * (pl[p].W / 8);
         d.wave_start = waves;
         d.block_off = blocks;
+        magic_u31(uint32_t(d.nbx), &d.nbx_m, &d.nbx_s);
         waves += (d.nblocks + 15) / 16;
         blocks += d.nblocks;
     }
     a->n_planes = np;
     a->blocks_per_frame = blocks;
     a->waves_per_frame = waves;
+    magic_u31(uint32_t(waves), &a->wpf_m, &a->wpf_s);
     a->r = r;
     a->step = step;
     a->inv_step = step ? float(1.0 / step) : 0.f;
@@ -410,10 +433,41 @@ static adct_status stream_impl(const uint8_t *frames, int64_t frame_stride, int 
     st = zero_u64(sse, int64_t(n_frames) * n_planes, s);
     if (st) return st;
     if (pr.runtime) return launch_codec_rt(pr.band, pr.quant, false, kEvaluate, a, pr.rt, wpf * n_frames, s);
-    return launch_codec(t, pr.band, pr.quant, kEvaluate, a, wpf * n_frames, s);
+    return launch_codec(t, pr.band, pr.quant, kEvaluate, a, pr.qt, wpf * n_frames, s);
 }
 
 extern "C" {
+
+adct_status adct_stream_bandwidth_probe(const uint8_t *frames, int64_t frame_stride, int n_frames,
+                                        const adct_plane *planes, int n_planes, int r, int16_t *coef,
+                                        uint8_t *recon, int64_t frame_stride_out, adct_stream_t stream) {
+    if (!frames || !planes) return fail(ADCT_EINVAL, "frames and planes are required");
+    if (n_frames < 1) return fail(ADCT_ERANGE, "n_frames must be >= 1");
+    if (n_planes < 1 || n_planes > kMaxPlanes) return fail(ADCT_ERANGE, "n_planes must be in [1, 4]");
+    if (frame_stride < 0 || (frame_stride & 7)) return fail(ADCT_EDIM, "frame_stride must be a non-negative multiple of 8");
+    if (recon && (frame_stride_out < 0 || (frame_stride_out & 7) || !aligned(recon, 8)))
+        return fail(ADCT_EDIM, "recon must be 8-byte aligned with a frame stride multiple of 8");
+    if (coef && !aligned(coef, 4)) return fail(ADCT_EDIM, "coef must be 4-byte aligned");
+    for (int p = 0; p < n_planes; ++p) {
+        adct_status st = check_plane(frames, planes[p].offset, planes[p].H, planes[p].W, planes[p].pitch, "plane");
+        if (st) return st;
+    }
+    CodecArgs a;
+    memset(&a, 0, sizeof(a));
+    Prepared pr;
+    adct_status st = prepare(ADCT_T1, nullptr, r, 0, false, &pr, &a);
+    if (st) return st;
+    const int wpf = setup_planes(&a, planes, n_planes);
+    if (int64_t(wpf) * n_frames >= (int64_t(1) << 31) / 4) return fail(ADCT_EDIM, "stream too large for one launch");
+    a.in = frames;
+    a.out = recon;
+    a.coef = coef;
+    a.fs_in = frame_stride;
+    a.fs_out = frame_stride_out;
+    a.n_frames = n_frames;
+    a.r = r;
+    return launch_codec(ADCT_T1, pr.band, false, kProbe, a, pr.qt, wpf * n_frames, reinterpret_cast<hipStream_t>(stream));
+}
 
 const char *adct_last_error(void) { return g_err.c_str(); }
 
@@ -499,7 +553,7 @@ adct_status adct_encode_blocks(const uint8_t *img, int H, int W, int pitch,
     a.r = r;
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     if (pr.runtime) return launch_codec_rt(pr.band, pr.quant, false, kEncode, a, pr.rt, waves, hs);
-    return launch_codec(t, pr.band, pr.quant, kEncode, a, waves, hs);
+    return launch_codec(t, pr.band, pr.quant, kEncode, a, pr.qt, waves, hs);
 }
 
 adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled,
@@ -560,7 +614,7 @@ adct_status adct_decode_blocks(const int16_t *coef_int, const float *coef_scaled
     a.n_frames = 1;
     a.r = r;
     if (pr.runtime) return launch_codec_rt(pr.band, pr.quant, false, kDecode, a, pr.rt, waves, hs);
-    return launch_codec(t, pr.band, pr.quant, kDecode, a, waves, hs);
+    return launch_codec(t, pr.band, pr.quant, kDecode, a, pr.qt, waves, hs);
 }
 
 adct_status adct_evaluate_stream(const uint8_t *frames, int64_t frame_stride, int n_frames,

@@ -191,7 +191,25 @@ struct PlaneArg {
     int32_t nblocks;    // blocks in the plane
     int32_t wave_start; // first wave of this plane inside a frame
     int32_t block_off;  // first block of this plane inside a frame
+    uint32_t nbx_m;     // n / nbx = umulhi(n, nbx_m) >> nbx_s for 0 <= n < 2^31
+    int32_t nbx_s;      //   (nbx_s < 0: nbx == 1)
 };
+
+// Exact division of 0 <= n < 2^31 by a wave-uniform divisor d through a
+// multiply-high and a shift (Granlund-Montgomery with a 32-bit multiplier):
+// with l = ceil(log2 d), m = ceil(2^(31 + l) / d) < 2^32 and n / d =
+// (n m) >> (31 + l).  Filled on the host (magic_u31), used by the tile walks.
+inline void magic_u31(uint32_t d, uint32_t *m, int32_t *s) {
+    if (d <= 1) {
+        *m = 0;
+        *s = -1;
+        return;
+    }
+    int l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    *m = uint32_t(((uint64_t(1) << (31 + l)) + d - 1) / d);
+    *s = l - 1;
+}
 
 struct CodecArgs {
     const uint8_t *in;
@@ -212,6 +230,18 @@ struct CodecArgs {
     float inv_step_f;    // 1 / step
     double inv_step_d;   // 1 / step
     double step_d;       // step
+    uint32_t wpf_m;      // division by waves_per_frame (see magic_u31)
+    int32_t wpf_s;
+};
+
+// Quantiser constants of the built-in codec kernels per zig-zag position z
+// (a second kernel argument; zero when there is no quantiser), with
+// d = step mu for a class n_k n_l = mu^2.
+struct QuantTables {
+    float qc1[64];       // 1 / d                       (rational classes)
+    float qc2[64];       // (d + 1/2) / (2 d)           (rational classes)
+    double qinv[64];     // s_k s_l / step              (irrational classes)
+    double qdeq[64];     // step s_k s_l: dequantised B = q qdeq
 };
 
 struct DctArgs {
@@ -229,12 +259,16 @@ struct DctArgs {
     int32_t r;
     int32_t step;
     float inv_step;
+    int32_t wpf_s;             // division by waves_per_frame (see magic_u31)
+    uint32_t wpf_m;
     int32_t pad;
     PlaneArg pl[kMaxPlanes];   // wave_start counts 16-block tiles
     float C[64];               // orthonormal DCT-II, C[8k + x]
 };
 
-enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2 };
+// kProbe: the loads and stores of kEvaluate without its arithmetic (the
+// achievable HBM rate of the codec's read / write mix).
+enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2, kProbe = 3 };
 
 // Constants of an integer matrix given at run time (ADCT_CUSTOM, and the
 // float-coefficient decode of the built-in matrices), a second kernel argument
@@ -264,6 +298,6 @@ adct_status launch_dct(Mode mode, const DctArgs &a, int total_waves, hipStream_t
 int codec_wgs_per_cu();
 
 adct_status launch_codec(int tid, int band, bool quant, Mode mode, const CodecArgs &a,
-                         int total_waves, hipStream_t s);
+                         const QuantTables &q, int total_waves, hipStream_t s);
 
 }  // namespace adct

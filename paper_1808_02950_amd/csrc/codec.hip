@@ -139,9 +139,101 @@ __device__ __forceinline__ int rne_div_clip(int n) {
 // 64 consecutive blocks of one plane of one frame) and issues the loads of its
 // next tile before it transforms the current one.
 
+// Store the r retained coefficients C of the lane's block (zig-zag order) at
+// coef[gblk * r ...].  A full tile's coefficients are one contiguous run of
+// 128 r bytes: for even r whose dword stride r/2 is not a multiple of 4 (so
+// the LDS writes are free of bank conflicts beyond two-way) and a 16-byte
+// aligned run, they go through a per-wave LDS slice and leave as 16-byte
+// stores that cover whole lines, instead of r/2 scattered 4-byte stores a lane.
+template <int NZ>
+__device__ __forceinline__ void store_coef_tile(const CodecArgs &a, const Tile &t, const PlaneArg &P,
+                                                int64_t gblk, const int (&C)[8][8]) {
+    if (!a.coef) return;
+    const int lane = int(threadIdx.x & 63);
+    const int64_t run0 = (gblk - lane) * a.r;           // first int16 of the tile
+    const bool staged = (a.r & 1) == 0 && ((a.r >> 1) & 3) != 0 && t.b - lane + 64 <= P.nblocks &&
+                        ((reinterpret_cast<uintptr_t>(a.coef + run0) & 15) == 0);
+    if (staged) {
+        __shared__ uint32_t stage[4][NZ * 32];
+        uint32_t *slice = stage[threadIdx.x >> 6];
+        const int half_r = a.r >> 1;
+#pragma unroll
+        for (int z = 0; z < NZ; z += 2) {
+            if (z + 1 < a.r) {
+                const int k0 = kZZ[z] >> 3, l0 = kZZ[z] & 7;
+                const int k1 = kZZ[z + 1] >> 3, l1 = kZZ[z + 1] & 7;
+                slice[lane * half_r + (z >> 1)] =
+                    (uint32_t(C[k0][l0]) & 0xffffu) | (uint32_t(C[k1][l1]) << 16);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int chunks = 8 * a.r;                      // 16-byte pieces of the run
+        u32x4 *gdst = reinterpret_cast<u32x4 *>(a.coef + run0);
+        for (int c = lane; c < chunks; c += 64)
+            __builtin_nontemporal_store(reinterpret_cast<const u32x4 *>(slice)[c], gdst + c);
+        __builtin_amdgcn_wave_barrier();
+        return;
+    }
+    if (!t.active) return;
+    int16_t *dst = a.coef + gblk * a.r;
+    if (a.r == NZ && (NZ & 1) == 0) {             // whole band, no per-entry test
+#pragma unroll
+        for (int z = 0; z < NZ; z += 2) {
+            const int k0 = kZZ[z] >> 3, l0 = kZZ[z] & 7;
+            const int k1 = kZZ[z + 1] >> 3, l1 = kZZ[z + 1] & 7;
+            const uint32_t pk = (uint32_t(C[k0][l0]) & 0xffffu) | (uint32_t(C[k1][l1]) << 16);
+            __builtin_nontemporal_store(pk, (uint32_t *)(dst + z));
+        }
+    } else if ((a.r & 1) == 0) {
+#pragma unroll
+        for (int z = 0; z < NZ; z += 2) {
+            if (z + 1 < a.r) {
+                const int k0 = kZZ[z] >> 3, l0 = kZZ[z] & 7;
+                const int k1 = kZZ[z + 1] >> 3, l1 = kZZ[z + 1] & 7;
+                const uint32_t pk = (uint32_t(C[k0][l0]) & 0xffffu) | (uint32_t(C[k1][l1]) << 16);
+                __builtin_nontemporal_store(pk, (uint32_t *)(dst + z));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int z = 0; z < NZ; ++z)
+            if (z < a.r) dst[z] = int16_t(C[kZZ[z] >> 3][kZZ[z] & 7]);
+    }
+}
+
+// The bandwidth probe: the loads and stores of an evaluation with no
+// arithmetic.  The reconstruction receives the input pixels, the coefficients
+// receive bytes of them.
+template <int BAND>
+__device__ __forceinline__ void probe_tile(const CodecArgs &a, const Tile &t, const uint32_t (&pix)[8][2]) {
+    constexpr int NZ = (BAND >= 14) ? 64 : (BAND + 1) * (BAND + 2) / 2;
+    const PlaneArg &P = a.pl[t.p];
+    const int64_t gblk = int64_t(t.f) * a.blocks_per_frame + P.block_off + t.b;
+    int C[8][8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int l = 0; l < 8; ++l) C[k][l] = int(pix[(8 * k + l) & 7][((8 * k + l) >> 3) & 1] >> (l & 1 ? 16 : 0));
+    store_coef_tile<NZ>(a, t, P, gblk, C);
+    uint8_t *dst = a.out ? a.out + int64_t(t.f) * a.fs_out + P.out_off + t.out_off : nullptr;
+    if (t.active && dst) {
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            u32x2 v;
+            v.x = pix[x][0];
+            v.y = pix[x][1];
+            __builtin_nontemporal_store(v, (u32x2 *)(dst + x * P.pitch_out));
+        }
+    }
+}
+
 template <int ID, int BAND, bool QUANT, int MODE>
-__device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
+__device__ __forceinline__ void process_tile(const CodecArgs &a, const QuantTables &qt, const Tile &t,
                                              const uint32_t (&pix)[8][2]) {
+    if constexpr (MODE == kProbe) {
+        probe_tile<BAND>(a, t, pix);
+        return;
+    }
     constexpr int KB = BAND + 1 < 8 ? BAND + 1 : 8;  // rows / columns touched
     const PlaneArg &P = a.pl[t.p];
     const bool active = t.active;
@@ -187,38 +279,14 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
             const int k = kZZ[z] >> 3, l = kZZ[z] & 7;
             int v = Y[k][l];
             if constexpr (QUANT) {
-                const int mu = Tf<ID>::mu(k, l);
-                v = mu ? quant_rational(v, a.step, mu, float(0.5 / mu), a.inv_step_f)
-                       : quant_irrational(v, Tf<ID>::skl(k, l), a.inv_step_d);
+                if (Tf<ID>::mu(k, l) != 0)
+                    v = quant_rational_f(v, qt.qc1[z], qt.qc2[z]);
+                else
+                    v = rne_i32(double(v) * qt.qinv[z]);   // never a half: see quant_irrational
             }
             C[k][l] = (z < a.r) ? v : 0;
         }
-        if (active && a.coef) {
-            int16_t *dst = a.coef + gblk * a.r;
-            if (a.r == NZ && (NZ & 1) == 0) {             // whole band, no per-entry test
-#pragma unroll
-                for (int z = 0; z < NZ; z += 2) {
-                    const int k0 = kZZ[z] >> 3, l0 = kZZ[z] & 7;
-                    const int k1 = kZZ[z + 1] >> 3, l1 = kZZ[z + 1] & 7;
-                    const uint32_t pk = (uint32_t(C[k0][l0]) & 0xffffu) | (uint32_t(C[k1][l1]) << 16);
-                    __builtin_nontemporal_store(pk, (uint32_t *)(dst + z));
-                }
-            } else if ((a.r & 1) == 0) {
-#pragma unroll
-                for (int z = 0; z < NZ; z += 2) {
-                    if (z + 1 < a.r) {
-                        const int k0 = kZZ[z] >> 3, l0 = kZZ[z] & 7;
-                        const int k1 = kZZ[z + 1] >> 3, l1 = kZZ[z + 1] & 7;
-                        const uint32_t pk = (uint32_t(C[k0][l0]) & 0xffffu) | (uint32_t(C[k1][l1]) << 16);
-                        __builtin_nontemporal_store(pk, (uint32_t *)(dst + z));
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int z = 0; z < NZ; ++z)
-                    if (z < a.r) dst[z] = int16_t(C[kZZ[z] >> 3][kZZ[z] & 7]);
-            }
-        }
+        store_coef_tile<NZ>(a, t, P, gblk, C);
         if (active && a.coef_f) {
             float *dst = a.coef_f + gblk * a.r;
 #pragma unroll
@@ -281,7 +349,7 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
             for (int l = 0; l < KB; ++l)
                 // q step is exact in float64 (|q| < 2^15, step < 2^16) and needs no
                 // quarter-rate 32-bit integer multiply
-                Yd[k][l] = (k + l <= BAND) ? double(C[k][l]) * a.step_d * Tf<ID>::skl(k, l) : 0.0;
+                Yd[k][l] = (k + l <= BAND) ? double(C[k][l]) * qt.qdeq[zz_pos(k, l)] : 0.0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             double yin0[8], yin1[8];
@@ -335,7 +403,7 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const Tile &t,
 }
 
 template <int ID, int BAND, bool QUANT, int MODE>
-__global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
+__global__ __launch_bounds__(256) void k_codec(const CodecArgs a, const QuantTables qt) {
     const int lane = threadIdx.x & 63;
     const int total = a.n_frames * a.waves_per_frame;
     const int stride = int(gridDim.x) * 4;
@@ -354,14 +422,14 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
         bool more = nxt < total;                           // wave-uniform
         tb = tile_of(a, more ? nxt : gw, lane);
         if constexpr (MODE != kDecode) load_tile(a, tb, pb);
-        process_tile<ID, BAND, QUANT, MODE>(a, ta, pa);
+        process_tile<ID, BAND, QUANT, MODE>(a, qt, ta, pa);
         if (!more) break;
         gw = nxt;
         nxt = gw + stride;
         more = nxt < total;
         ta = tile_of(a, more ? nxt : gw, lane);
         if constexpr (MODE != kDecode) load_tile(a, ta, pa);
-        process_tile<ID, BAND, QUANT, MODE>(a, tb, pb);
+        process_tile<ID, BAND, QUANT, MODE>(a, qt, tb, pb);
         if (!more) break;
         gw = nxt;
     }
@@ -369,41 +437,44 @@ __global__ __launch_bounds__(256) void k_codec(const CodecArgs a) {
 
 
 template <int ID, int BAND, bool QUANT, int M>
-adct_status launch_one(const CodecArgs &a, int total_waves, hipStream_t s) {
+adct_status launch_one(const CodecArgs &a, const QuantTables &q, int total_waves, hipStream_t s) {
     auto kern = k_codec<ID, BAND, QUANT, M>;
     int grid = 0;
     adct_status st = persistent_grid(kern, total_waves, &grid);
     if (st) return st;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, a, q);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }
 
 template <int ID, int BAND, bool QUANT>
-adct_status launch_mode(Mode mode, const CodecArgs &a, int total_waves, hipStream_t s) {
-    if (mode == kEncode) return launch_one<ID, BAND, QUANT, kEncode>(a, total_waves, s);
-    if (mode == kDecode) return launch_one<ID, BAND, QUANT, kDecode>(a, total_waves, s);
-    return launch_one<ID, BAND, QUANT, kEvaluate>(a, total_waves, s);
+adct_status launch_mode(Mode mode, const CodecArgs &a, const QuantTables &q, int total_waves, hipStream_t s) {
+    if (mode == kEncode) return launch_one<ID, BAND, QUANT, kEncode>(a, q, total_waves, s);
+    if (mode == kDecode) return launch_one<ID, BAND, QUANT, kDecode>(a, q, total_waves, s);
+    return launch_one<ID, BAND, QUANT, kEvaluate>(a, q, total_waves, s);
 }
 
 template <int ID>
-adct_status launch_tf(int band, bool quant, Mode mode, const CodecArgs &a, int tw, hipStream_t s) {
-    if (band <= 3) return quant ? launch_mode<ID, 3, true>(mode, a, tw, s) : launch_mode<ID, 3, false>(mode, a, tw, s);
-    return quant ? launch_mode<ID, 14, true>(mode, a, tw, s) : launch_mode<ID, 14, false>(mode, a, tw, s);
+adct_status launch_tf(int band, bool quant, Mode mode, const CodecArgs &a, const QuantTables &q, int tw, hipStream_t s) {
+    if (band <= 3) return quant ? launch_mode<ID, 3, true>(mode, a, q, tw, s) : launch_mode<ID, 3, false>(mode, a, q, tw, s);
+    return quant ? launch_mode<ID, 14, true>(mode, a, q, tw, s) : launch_mode<ID, 14, false>(mode, a, q, tw, s);
 }
 
 }  // namespace
 
 adct_status launch_codec(int tid, int band, bool quant, Mode mode, const CodecArgs &a,
-                         int total_waves, hipStream_t s) {
+                         const QuantTables &q, int total_waves, hipStream_t s) {
     if (total_waves <= 0) return ADCT_OK;
+    if (mode == kProbe)
+        return band <= 3 ? launch_one<ADCT_T1, 3, false, kProbe>(a, q, total_waves, s)
+                         : launch_one<ADCT_T1, 14, false, kProbe>(a, q, total_waves, s);
     switch (tid) {
-        case ADCT_T1: return launch_tf<ADCT_T1>(band, quant, mode, a, total_waves, s);
-        case ADCT_T2: return launch_tf<ADCT_T2>(band, quant, mode, a, total_waves, s);
-        case ADCT_LO: return launch_tf<ADCT_LO>(band, quant, mode, a, total_waves, s);
-        case ADCT_T6: return launch_tf<ADCT_T6>(band, quant, mode, a, total_waves, s);
-        case ADCT_RDCT: return launch_tf<ADCT_RDCT>(band, quant, mode, a, total_waves, s);
-        case ADCT_T4: return launch_tf<ADCT_T4>(band, quant, mode, a, total_waves, s);
+        case ADCT_T1: return launch_tf<ADCT_T1>(band, quant, mode, a, q, total_waves, s);
+        case ADCT_T2: return launch_tf<ADCT_T2>(band, quant, mode, a, q, total_waves, s);
+        case ADCT_LO: return launch_tf<ADCT_LO>(band, quant, mode, a, q, total_waves, s);
+        case ADCT_T6: return launch_tf<ADCT_T6>(band, quant, mode, a, q, total_waves, s);
+        case ADCT_RDCT: return launch_tf<ADCT_RDCT>(band, quant, mode, a, q, total_waves, s);
+        case ADCT_T4: return launch_tf<ADCT_T4>(band, quant, mode, a, q, total_waves, s);
         default: return fail(ADCT_ENOTSUP, "transform not implemented by the integer codec");
     }
 }

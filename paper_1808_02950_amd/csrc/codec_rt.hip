@@ -3,9 +3,8 @@
 // other T with orthogonal rows), and the float-coefficient decode of the
 // built-in matrices.
 //
-// The pipeline and the tiling are those of the built-in codec (one lane per
-// 8x8 block, a wave per 64 consecutive blocks, a persistent grid that loads the
-// next tile before transforming the current one).  What changes is the
+// The tiling is that of the built-in codec (one lane per 8x8 block, a wave per
+// 64 consecutive blocks), without its persistent grid.  What changes is the
 // arithmetic: nothing about T is known at compile time, so both passes are
 // plain 8-term products with wave-uniform entries, the exact inverse works on
 // 64-bit numerators over L = lcm(n)^2 with a run-time division, and every
@@ -206,43 +205,25 @@ __device__ __forceinline__ void process_tile_rt(const CodecArgs &a, const RtMatA
     }
 }
 
+// One 64-block tile per wave and no persistent loop: the kernel is straight-line
+// code, so the table values it reads from its argument are loaded where they
+// are needed rather than kept live across iterations.
 template <int BAND, bool QUANT, int MODE, bool FIN>
 __global__ __launch_bounds__(256) void k_codec_rt(const CodecArgs a, const RtMatArgs m) {
     const int lane = threadIdx.x & 63;
     const int total = a.n_frames * a.waves_per_frame;
-    const int stride = int(gridDim.x) * 4;
-    int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     if (gw >= total) return;
-    // two pixel buffers in turn, as in the built-in codec: the next tile's
-    // loads are issued (on every pass) before the current tile is transformed
-    uint32_t pa[8][2], pb[8][2];
-    Tile ta = tile_of(a, gw, lane), tb = ta;
-    if constexpr (MODE != kDecode) load_tile(a, ta, pa);
-    while (true) {
-        int nxt = gw + stride;
-        bool more = nxt < total;
-        tb = tile_of(a, more ? nxt : gw, lane);
-        if constexpr (MODE != kDecode) load_tile(a, tb, pb);
-        process_tile_rt<BAND, QUANT, MODE, FIN>(a, m, ta, pa);
-        if (!more) break;
-        gw = nxt;
-        nxt = gw + stride;
-        more = nxt < total;
-        ta = tile_of(a, more ? nxt : gw, lane);
-        if constexpr (MODE != kDecode) load_tile(a, ta, pa);
-        process_tile_rt<BAND, QUANT, MODE, FIN>(a, m, tb, pb);
-        if (!more) break;
-        gw = nxt;
-    }
+    uint32_t pix[8][2];
+    const Tile t = tile_of(a, gw, lane);
+    if constexpr (MODE != kDecode) load_tile(a, t, pix);
+    process_tile_rt<BAND, QUANT, MODE, FIN>(a, m, t, pix);
 }
 
 template <int BAND, bool QUANT, int MODE, bool FIN>
 adct_status launch_rt_one(const CodecArgs &a, const RtMatArgs &m, int total_waves, hipStream_t s) {
-    auto kern = k_codec_rt<BAND, QUANT, MODE, FIN>;
-    int grid = 0;
-    adct_status st = persistent_grid(kern, total_waves, &grid);
-    if (st) return st;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, a, m);
+    const int64_t grid = (int64_t(total_waves) + 3) / 4;
+    hipLaunchKernelGGL((k_codec_rt<BAND, QUANT, MODE, FIN>), dim3(unsigned(grid)), dim3(256), 0, s, a, m);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }

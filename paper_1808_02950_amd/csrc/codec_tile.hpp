@@ -11,6 +11,7 @@ namespace adct {
 namespace {
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int byte_of(uint32_t w, int i) { return int((w >> (8 * i)) & 0xffu); }
 
@@ -21,6 +22,25 @@ __device__ __forceinline__ int rne_i32(double x) {
 }
 
 __device__ __forceinline__ int clamp255(int v) { return min(max(v, 0), 255); }
+
+// n / d for 0 <= n < 2^31 and a wave-uniform d, from its magic pair (m, s).
+__device__ __forceinline__ int udiv_magic(int n, uint32_t m, int s) {
+    return s < 0 ? n : int(__umulhi(uint32_t(n), m) >> s);
+}
+
+// round-half-away(Y / d) for d = step mu (a class n_k n_l = mu^2, where Y / d can
+// be an exact half), in float32: floor((2|Y| + d + 1/2) / (2d)) is the rounded
+// magnitude, and its argument |Y| / d + (d + 1/2) / (2d) lies at least 1/(4d)
+// from an integer, while c1 = 1/d and c2 = (d + 1/2)/(2d) in float32 and one fma
+// err by less than (2 x + 1) 2^-24 with x < |Y| / d + 1 -- below 1/(4d) whenever
+// |Y| + d < 2^21 (the host requires 2^20).  The sign of Y is copied onto the
+// quotient, whose truncation toward zero is then the signed level.
+__device__ __forceinline__ int quant_rational_f(int y, float c1, float c2) {
+    const float yf = float(y);
+    const float x = fmaf(fabsf(yf), c1, c2);
+    const float xs = __int_as_float(int((__float_as_uint(x) & 0x7fffffffu) | (__float_as_uint(yf) & 0x80000000u)));
+    return int(xs);
+}
 
 // round-half-away(Y / d), d = step * mu, for the classes where n_k n_l = mu^2
 // (Y / d can be an exact half): floor((2|Y| + d) / (2d)) from a float estimate
@@ -61,14 +81,14 @@ struct Tile {
 
 __device__ __forceinline__ Tile tile_of(const CodecArgs &a, int gw, int lane) {
     Tile t;
-    t.f = gw / a.waves_per_frame;
+    t.f = udiv_magic(gw, a.wpf_m, a.wpf_s);
     const int w = gw - t.f * a.waves_per_frame;
     int p = 0;
     while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
     t.p = p;
     const PlaneArg &P = a.pl[p];
     const int b0 = (w - P.wave_start) * 64;             // first block of the wave
-    const int by0 = b0 / P.nbx;
+    const int by0 = udiv_magic(b0, P.nbx_m, P.nbx_s);
     const int bx0 = b0 - by0 * P.nbx;
     t.b = b0 + lane;
     t.active = t.b < P.nblocks;

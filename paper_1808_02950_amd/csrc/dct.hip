@@ -60,19 +60,24 @@ struct DTile {
     uint32_t in_off, out_off;   // byte offset of the block's top-left pixel
 };
 
+// n / d for 0 <= n < 2^31 from the magic pair of a wave-uniform d.
+__device__ __forceinline__ int udiv_u31(int n, uint32_t m, int s) {
+    return s < 0 ? n : int(__umulhi(uint32_t(n), m) >> s);
+}
+
 // Tile gw of the launch: frame and plane are wave-uniform; the wave's first
-// block comes from one scalar division, and lane n's block is at most one
-// block-row further when the plane is at least 16 blocks wide.
+// block comes from two multiply-high divisions, and lane n's block is at most
+// one block-row further when the plane is at least 16 blocks wide.
 __device__ __forceinline__ DTile dtile_of(const DctArgs &a, int gw, int n) {
     DTile t;
-    t.f = gw / a.waves_per_frame;
+    t.f = udiv_u31(gw, a.wpf_m, a.wpf_s);
     const int w = gw - t.f * a.waves_per_frame;
     int p = 0;
     while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
     t.p = p;
     const PlaneArg &P = a.pl[p];
     const int b0 = (w - P.wave_start) * 16;
-    const int by0 = b0 / P.nbx;
+    const int by0 = udiv_u31(b0, P.nbx_m, P.nbx_s);
     const int bx0 = b0 - by0 * P.nbx;
     t.b = b0 + n;
     t.active = t.b < P.nblocks;

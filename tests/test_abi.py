@@ -109,6 +109,24 @@ def test_stream_argument_errors():
     assert lib.adct_evaluate_stream(FAKE, 256, 1, bad, 1, A.T1, None, 10, 0, None, None, 0, sse, None) == -2
 
 
+def test_bandwidth_probe_argument_errors():
+    planes = A.planes_struct([(0, 16, 16, 16)])
+    lib = A.lib()
+    assert lib.adct_stream_bandwidth_probe(None, 256, 1, planes, 1, 10, None, None, 0, None) == -1
+    assert lib.adct_stream_bandwidth_probe(FAKE, 256, 0, planes, 1, 10, None, None, 0, None) == -3
+    assert lib.adct_stream_bandwidth_probe(FAKE, 256, 1, planes, 1, 0, None, None, 0, None) == -3
+    bad = A.planes_struct([(4, 16, 16, 16)])
+    assert lib.adct_stream_bandwidth_probe(FAKE, 256, 1, bad, 1, 10, None, None, 0, None) == -2
+
+
+def test_plane_height_bound():
+    """Row offsets are formed with 24-bit multiplies, so planes of 2^24 rows or
+    more are refused (ADCT_EDIM) before any device work."""
+    big = A.planes_struct([(0, 1 << 24, 8, 8)])
+    sse = ctypes.c_void_p(8192)
+    assert A.lib().adct_evaluate_stream(FAKE, 0, 1, big, 1, A.T1, None, 10, 0, None, None, 0, sse, None) == -2
+
+
 def test_tie_free_quantiser_steps_accepted():
     lib = A.lib()
     for tid, step in [(A.T1, 8), (A.T1, 16), (A.T1, 24), (A.T4, 8), (A.T6, 40), (A.LO, 32)]:

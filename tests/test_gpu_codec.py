@@ -196,3 +196,28 @@ def test_device_argument_errors(cuda):
     with pytest.raises(A.AdctError) as e:
         A.encode_blocks(img, "LO", 10)                 # LO does not fit int16
     assert e.value.status == -4
+
+
+def test_bandwidth_probe_moves_the_stream_bytes(cuda):
+    """The bandwidth probe (the codec's loads and stores without its arithmetic)
+    copies every plane's pixels into recon and fills the coefficient run of every
+    block, leaving bytes outside the planes untouched."""
+    import torch
+    planes = [(0, 48, 64, 72), (48 * 72, 24, 32, 40)]
+    fbytes = 48 * 72 + 24 * 40
+    rng = np.random.Generator(np.random.PCG64(9))
+    frames = rng.integers(0, 255, size=(3, fbytes), dtype=np.uint8)     # no 0xffff byte pair
+    d = torch.from_numpy(frames).to(cuda)
+    recon = torch.full_like(d, 7)
+    nb = A.stream_blocks_per_frame(planes)
+    coef = torch.full((3 * nb * 10,), -1, dtype=torch.int16, device=cuda)
+    A.stream_bandwidth_probe(d, planes, 10, coef=coef, recon=recon)
+    rc = recon.cpu().numpy()
+    inside = np.zeros(fbytes, dtype=bool)
+    for off, h, w, pitch in planes:
+        for y in range(h):
+            inside[off + y * pitch: off + y * pitch + w] = True
+    assert np.array_equal(rc[:, inside], frames[:, inside])
+    assert np.all(rc[:, ~inside] == 7)
+    # every coefficient entry was written (with two pixel bytes, never 0xffff)
+    assert not np.any(coef.cpu().numpy() == -1)
