@@ -45,8 +45,10 @@ def build_stream(spec, dev):
     return frames
 
 
-def cpu_baseline(spec, n_frames: int, r: int, step: int):
-    """The CPU oracle, untuned, on the first n_frames frames (all planes)."""
+def cpu_baseline(spec, n_frames: int, r: int, step: int, gpu_lists=None):
+    """The CPU oracle, untuned, on the first n_frames frames (all planes): one
+    thread, then one process per available core (up to 16), with the host's
+    core count and CPU model; plus bounded samples of the other workloads."""
     from threadpoolctl import threadpool_limits
 
     from oracle import codec as Co
@@ -63,9 +65,166 @@ def cpu_baseline(spec, n_frames: int, r: int, step: int):
                 Co.evaluate(buf[o:o + h * w].reshape(h, w), M.T1, r, step)
                 samples += h * w
         dt = time.perf_counter() - t0
-    return {"value": samples / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_frames} of the {spec.n_frames} frames, all 3 planes, "
-                      f"T1 r={r} step {step}, encode+decode+SSE, one thread, {dt:.1f} s"}
+    host = host_info()
+    workers = max(1, min(16, host["affinity_cpus"] or 1))
+    v_all, dt_all, n_all = cpu_all_cores(spec, workers, 4, r, step)
+    out = {"value": samples / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {n_frames} of the {spec.n_frames} frames, all 3 planes, "
+                     f"T1 r={r} step {step}, encode+decode+SSE, one thread, {dt:.1f} s",
+           "blas_threads": 1, **host,
+           "all_cores": {"value": round(v_all, 2), "unit": "Mpixel/s", "cores": workers,
+                         "sample": f"{n_all} frames over {workers} single-threaded processes, {dt_all:.1f} s"}}
+    if gpu_lists is not None:
+        out["legs"] = cpu_legs(gpu_lists)
+    return out
+
+
+def host_info():
+    """Host cores and CPU model the CPU oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff}
+
+
+_POOL_STATE = {}
+
+
+def _pool_init(n_frames, r, step):
+    from threadpoolctl import threadpool_limits
+
+    from synth import video_base_planes, video_spec
+    spec = video_spec(n_frames=n_frames)
+    _POOL_STATE.update(spec=spec, bases=video_base_planes(spec), r=r, step=step,
+                       limits=threadpool_limits(1))
+
+
+def _pool_frame(f):
+    from oracle import codec as Co
+    from oracle import matrices as M
+    from synth import video_frame
+    st = _POOL_STATE
+    buf = video_frame(st["spec"], st["bases"], f)
+    n = 0
+    for (h, w), o in zip(st["spec"].plane_shapes, st["spec"].plane_offsets):
+        Co.evaluate(buf[o:o + h * w].reshape(h, w), M.T1, st["r"], st["step"])
+        n += h * w
+    return n
+
+
+def cpu_all_cores(spec, workers: int, frames_per_worker: int, r: int, step: int):
+    """The same oracle, one process per core (each single-threaded), over
+    frames_per_worker frames per process; returns (Mpixel/s, seconds, frames)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    n = workers * frames_per_worker
+    ctx = mp.get_context("spawn")
+    with ProcessPoolExecutor(workers, mp_context=ctx, initializer=_pool_init,
+                             initargs=(spec.n_frames, r, step)) as ex:
+        list(ex.map(_pool_frame, range(workers)))          # warm: bases built, imports done
+        t0 = time.perf_counter()
+        samples = sum(ex.map(_pool_frame, range(n)))
+        dt = time.perf_counter() - t0
+    return samples / dt / 1e6, dt, n
+
+
+def cpu_legs(gpu_lists):
+    """The CPU oracle on bounded samples of the other workloads (one thread),
+    each scaled to its unit and labelled with what was timed."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import batch as Ob
+    from oracle import codec as Co
+    from oracle import ctuples
+    from oracle import matrices as M
+    from oracle import postfilter as Of
+    from oracle import search as Os
+    from synth import ar1_image, batch_images, batch_specs, filter_params
+
+    legs = {}
+    with threadpool_limits(1):
+        img = ar1_image(512, 512, 0.95, seed=0)
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            Co.evaluate(img, M.T1, 10)
+        t_t1 = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Co.evaluate_dct(img, 10)
+        t_dct = (time.perf_counter() - t0) / reps
+        legs["single_512x512_r10"] = {"T1_us_per_call": round(t_t1 * 1e6, 1),
+                                      "DCT_us_per_call": round(t_dct * 1e6, 1),
+                                      "T1_Mpixel_per_s": round(img.size / t_t1 / 1e6, 2),
+                                      "sample": f"encode+decode+SSE of the 512x512 image, mean of {reps} calls"}
+
+        specs = sorted(batch_specs(), key=lambda b: b.h * b.w)[:1]
+        imgs = batch_images(specs)
+        names = ["DCT", "T1", "LO", "T6", "RDCT", "T4"]
+        t0 = time.perf_counter()
+        Ob.sse_table(imgs, names, 1, 63)
+        dt = time.perf_counter() - t0
+        px = sum(im.size for im in imgs)
+        all_px = sum(b.h * b.w for b in batch_specs())
+        legs["batch_45img_6tf_r1_63"] = {
+            "evaluations_per_s": round(len(imgs) * len(names) * 63 / dt, 1),
+            "Gpixel_evals_per_s": round(px * len(names) * 63 / dt / 1e9, 4),
+            "extrapolated_s_for_45_images": round(dt * all_px / px, 1),
+            "sample": f"the smallest of the 45 images ({px} pixels) x 6 transforms x r=1..63 in "
+                      f"{dt:.1f} s, extrapolated by pixel count"}
+
+        p4 = [0, 1, -1, 2, -2, 3, -3, 4, -4]
+        chunk = 1 << 21
+        t0 = time.perf_counter()
+        Os.topk_scan(p4[:5], 64, chunk=chunk)                    # warm the numpy paths
+        dt_small = time.perf_counter() - t0
+        # one chunk of the 9^8 space scanned as the oracle does, extrapolated
+        digs = np.array(Os.canonical_digits(p4), dtype=np.int64)
+        c = M.dct_matrix()
+        t0 = time.perf_counter()
+        idx = np.arange(1, 1 + chunk, dtype=np.int64)
+        cols = [(idx // 9 ** (7 - q)) % 9 for q in range(8)]
+        d = digs[np.stack(cols, axis=1)]
+        d = d[Os._gcd_rows(d) == 1].astype(np.float64)
+        cs = (d @ c.T) / np.sqrt(np.sum(d * d, axis=1))[:, None]
+        for row in range(8):
+            np.argpartition(-cs[:, row], 255)[:256]
+        dt = time.perf_counter() - t0
+        total = 9 ** 8 - 1
+        t0 = time.perf_counter()
+        _, n256 = ctuples.orthogonal_tuples([gpu_lists[r] for r in range(8)])
+        dt_tup = time.perf_counter() - t0
+        legs["search_topk_9pow8"] = {
+            "Gcand_rows_per_s": round(8 * chunk / dt / 1e9, 4),
+            "extrapolated_scan_s": round(dt * total / chunk, 1),
+            "tuples_k256_s": round(dt_tup, 3), "tuples_k256": int(n256),
+            "sample": f"{chunk} of the {total} candidates (digits, gcd, 8 cosines, per-row top 256) in "
+                      f"{dt:.2f} s, extrapolated; the C tuple DFS on the 8 top-256 lists; "
+                      f"5^8 warm-up scan {dt_small:.1f} s"}
+
+        pr = filter_params(0)
+        rng = np.random.Generator(np.random.PCG64(3))
+        x = rng.integers(0, 256, size=(2, 64, 64), dtype=np.uint8)
+        o = rng.integers(0, 256, size=(2, 64, 64), dtype=np.uint8)
+        t0 = time.perf_counter()
+        Of.loss_and_grad(pr, x, o)
+        dt = time.perf_counter() - t0
+        legs["postfilter_train"] = {
+            "patches_per_s": round(2 / dt, 2),
+            "extrapolated_epoch_s_200k_patches": round(dt / 2 * 200000, 0),
+            "sample": f"forward + backward of 2 patches of 64x64 in float64 ({dt:.2f} s), "
+                      f"extrapolated to one epoch of 200,000 patches"}
+    return legs
 
 
 def measured_traffic():
@@ -272,6 +431,62 @@ def coding_gain_row():
             "T1_over_LO_loss_at_0.95": round(float(d[0, i95] / d[1, i95]), 3)}
 
 
+# The paper's own hardware figures (Sec. 5.2 results table): the 1-D 8-point
+# cores on a Xilinx Virtex-6 XC6VLX240T-1FFG1156 (ML605 board), fixed point,
+# checked by hardware co-simulation on 100,000 random input vectors.  Context
+# only: a different device, a 1-D core, and no 2-D block coding throughput.
+FPGA_CONTEXT = {
+    "device": "Xilinx Virtex-6 XC6VLX240T-1FFG1156 (ML605)",
+    "what": "1-D 8-point transform core, fixed point; paper Sec. 5.2 results table",
+    "T1": {"CLB": 135, "FF": 408, "T_cpd_ns": 1.750, "F_max_MHz": 571, "D_p_mW_per_GHz": 2.74, "Q_p_W": 3.471},
+    "T_LO": {"CLB": 114, "FF": 349, "T_cpd_ns": 1.900, "F_max_MHz": 526, "D_p_mW_per_GHz": 2.82,
+             "Q_p_W": 3.468},
+    "T6": {"CLB": 125, "FF": 389, "T_cpd_ns": 2.100, "F_max_MHz": 476, "D_p_mW_per_GHz": 2.57, "Q_p_W": 3.460},
+    "note": "at one 8-point vector per clock the T1 core would do 571 M 1-D transforms/s, i.e. 35.7 M "
+            "8x8 blocks/s (2.28 Gpixel/s) for a 2-D transform; a derived figure the paper does not "
+            "state (it assumes full pipelining and excludes I/O)",
+}
+
+
+def single_image_row():
+    """The single 512x512 image (seeded AR(1), rho 0.95): one call's latency for
+    T1 at r = 10 (zonal) and the exact DCT, with PSNR; the image fits in the
+    Infinity Cache, so this is a latency figure, not a roofline case."""
+    import torch
+
+    import paper_1808_02950_amd as A
+    from synth import ar1_image
+
+    img = torch.from_numpy(ar1_image(512, 512, 0.95, seed=0)).cuda()
+    rec = torch.empty_like(img)
+    coef = torch.empty((4096, 10), dtype=torch.int16, device=img.device)
+    res = {}
+    for t in ("T1", "DCT"):
+        c = coef if t == "T1" else None
+        ev = A.evaluate_coding(img, t, 10, coef_int=c, recon=rec)
+        v = img.view(1, -1)
+        rv = rec.view(1, -1)
+        sse_t = torch.empty((1, 1), dtype=torch.int64, device=img.device)
+        pl = [(0, 512, 512, 512)]
+        A.evaluate_stream(v, pl, t, 10, coef=c, recon=rv, sse=sse_t)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = 200
+        e0.record()
+        for _ in range(n):
+            A.evaluate_stream(v, pl, t, 10, coef=c, recon=rv, sse=sse_t)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / n * 1e3
+        t0 = time.perf_counter()
+        for _ in range(50):
+            A.evaluate_coding(img, t, 10, coef_int=c, recon=rec)
+        us_sync = (time.perf_counter() - t0) / 50 * 1e6
+        res[t] = {"us_per_launch": round(us, 2), "us_per_call_with_psnr_sync": round(us_sync, 1),
+                  "Mpixel_per_s": round(img.numel() / (us / 1e6) / 1e6, 1), "psnr": round(ev.psnr, 4)}
+    return res
+
+
 FILTER_FLOP_PER_PX = 2 * (9 * 32 + 288 * 32 + 288)   # 19,584: forward MACs x 2, per output pixel
 # SSIM per map position: two separable 11-tap passes over 5 maps (x, y, x^2, y^2, xy)
 # as multiply-adds, plus the formula (about 20 operations)
@@ -388,6 +603,8 @@ def main():
     ap.add_argument("--filter-patches", type=int, default=200000,
                     help="training patches of the post-filter (0 skips the filter row)")
     ap.add_argument("--filter-steps", type=int, default=6000)
+    ap.add_argument("--codec-only", action="store_true",
+                    help="time only the headline codec step and its bandwidth probe (profiling runs)")
     ap.add_argument("--schedule", type=int, default=0,
                     help="resident workgroups per CU of the codec grid (0 = occupancy limit, "
                          "-1 = one tile per wave)")
@@ -399,7 +616,7 @@ def main():
         sys.exit(2)
 
     # training images are drawn before the GPU is touched
-    fdata = filter_images(args.filter_patches, 4096) if args.filter_patches else None
+    fdata = filter_images(args.filter_patches, 4096) if args.filter_patches and not args.codec_only else None
 
     import numpy as np
     import torch
@@ -458,6 +675,30 @@ def main():
         return frame_, planes_
 
     psnr_frame, psnr_planes = psnrs(sse)
+
+    # the HBM ceiling of this read / write mix: the same loads and stores without
+    # the arithmetic (adct_stream_bandwidth_probe), timed the same way
+    for _ in range(2):
+        A.stream_bandwidth_probe(frames, planes, r, coef=coef, recon=recon)
+    torch.cuda.synchronize()
+    evp0 = torch.cuda.Event(enable_timing=True)
+    evp1 = torch.cuda.Event(enable_timing=True)
+    evp0.record()
+    for _ in range(args.steps):
+        A.stream_bandwidth_probe(frames, planes, r, coef=coef, recon=recon)
+    evp1.record()
+    torch.cuda.synchronize()
+    probe_ms = evp0.elapsed_time(evp1) / args.steps
+    ceiling = alg_bytes / (probe_ms / 1e3) / 1e9
+    # restore the codec's outputs (the probe overwrote them)
+    step_once()
+
+    if args.codec_only:
+        print(json.dumps({"metric": "codec-only profiling run", "kernel_ms": round(kernel_ms, 4),
+                          "probe_ms": round(probe_ms, 4), "achieved_GBps": round(achieved, 1),
+                          "ceiling_GBps": round(ceiling, 1), "ms_per_step": round(ms_per_step, 4)}),
+              flush=True)
+        return
 
     # exact-DCT comparator (float32-exact products on the matrix cores) on the
     # same stream, timed apart
@@ -582,7 +823,13 @@ def main():
         "inverse_decoder_SDCT": inverse_row,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
-                     "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes},
+                     "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes,
+                     "ceiling_GBps": round(ceiling, 1), "ceiling_kernel_ms": round(probe_ms, 4),
+                     "frac_of_ceiling": round(achieved / ceiling, 4),
+                     "ceiling_how": "adct_stream_bandwidth_probe: the codec's loads and stores for the "
+                                    "same launch without the arithmetic"},
+        "single_512x512": single_image_row(),
+        "context_fpga_paper": FPGA_CONTEXT,
     }
     out["other_rows"] = other_rows()
     if fdata is not None:
@@ -590,7 +837,9 @@ def main():
                                                      sse_dct, npix, kernel_ms)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_frames, spec.n_frames), r, step)
+        vec256, _, _ = A.search_topk([0, 1, -1, 2, -2, 3, -3, 4, -4], 256)
+        out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_frames, spec.n_frames), r, step,
+                                           gpu_lists=[vec256[q] for q in range(8)])
     print(json.dumps(out), flush=True)
 
 
