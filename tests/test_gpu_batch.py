@@ -95,7 +95,8 @@ def test_batch_graph_replays(cuda, small_set):
 
 def test_batch_45_images_sampled(cuda):
     """The 45-image workload (uneven sizes up to 2048 x 1536): one plan, then
-    sampled (image, transform, r) entries against the oracle."""
+    sampled (image, transform, r) entries of the small images and every
+    transform at r = 1, 10, 40, 63 of the three largest against the oracle."""
     specs = batch_specs()
     images = batch_images(specs)
     base, planes = _pack(images, cuda)
@@ -115,6 +116,18 @@ def test_batch_45_images_sampled(cuda):
             assert abs(int(sse[i, t, r - 1]) - ref) <= 1e-6 * ref + 2
         else:
             assert int(sse[i, t, r - 1]) == ref, (i, names[t], r)
+    # the three largest images (up to 2048 x 1536), every transform, r across the scan
+    large = sorted(range(len(images)), key=lambda i: images[i].size)[-3:]
+    for i in large:
+        img = images[i]
+        for t, name in enumerate(names):
+            for r in (1, 10, 40, 63):
+                ref = (Co.evaluate_dct(img, r) if name == "DCT"
+                       else Co.evaluate(img, M.TRANSFORMS[name], r))["sse"]
+                if name == "DCT":
+                    assert abs(int(sse[i, t, r - 1]) - ref) <= 1e-6 * ref + 2, (i, name, r)
+                else:
+                    assert int(sse[i, t, r - 1]) == ref, (i, name, r)
     plan.close()
 
 
