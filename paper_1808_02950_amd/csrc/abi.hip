@@ -263,17 +263,20 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
         }
     memset(&out->qt, 0, sizeof(out->qt));
     if (out->quant) {
-        for (int z = 0; z < 64; ++z) {
-            const int k = kZZ[z] >> 3, l = kZZ[z] & 7;
-            const int64_t prod = int64_t(n[k]) * n[l];
-            const int64_t mu = int64_t(llround(sqrt(double(prod))));
-            const double skl = inv_sqrt_newton(prod);
-            const double d = double(quant_step) * double(mu);
-            out->qt.qc1[z] = (mu * mu == prod) ? float(1.0 / d) : 0.f;
-            out->qt.qc2[z] = (mu * mu == prod) ? float((d + 0.5) / (2.0 * d)) : 0.f;
-            out->qt.qinv[z] = skl / double(quant_step);
-            out->qt.qdeq[z] = double(quant_step) * skl;
-        }
+        int32_t nn[8];
+        for (int k = 0; k < 8; ++k) nn[k] = n[k];
+        for (int k = 0; k < 8; ++k)
+            for (int l = 0; l < 8; ++l) {
+                const int c = class_of(nn, k, l);
+                const int64_t prod = int64_t(n[k]) * n[l];
+                const int64_t mu = int64_t(llround(sqrt(double(prod))));
+                const double skl = inv_sqrt_newton(prod);
+                const double d = double(quant_step) * double(mu);
+                out->qt.qc1[c] = (mu * mu == prod) ? float(1.0 / d) : 0.f;
+                out->qt.qc2[c] = (mu * mu == prod) ? float((d + 0.5) / (2.0 * d)) : 0.f;
+                out->qt.qinv[c] = skl / double(quant_step);
+                out->qt.qdeq[c] = double(quant_step) * skl;
+            }
     }
     if (out->runtime) {
         adct_status st = build_rt(out->m, &out->rt);

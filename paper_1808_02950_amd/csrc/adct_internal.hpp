@@ -120,6 +120,26 @@ constexpr double inv_sqrt_newton(int64_t v) {
     return 1.0 / r;
 }
 
+// Scale classes: the distinct values of n_k n_l of a matrix, numbered in
+// increasing order (at most 36 for 8 distinct row norms).  The quantiser
+// constants are per class, so a kernel holds one copy of each.
+constexpr int kMaxClasses = 36;
+
+// class index of n_k n_l among the distinct products of n (ascending)
+constexpr int class_of(const int32_t (&n)[8], int k, int l) {
+    const int64_t v = int64_t(n[k]) * n[l];
+    int below = 0;
+    for (int a = 0; a < 64; ++a) {
+        const int64_t u = int64_t(n[a >> 3]) * n[a & 7];
+        if (u >= v) continue;
+        bool first = true;                     // count each distinct smaller value once
+        for (int c = 0; c < a && first; ++c)
+            if (int64_t(n[c >> 3]) * n[c & 7] == u) first = false;
+        below += first ? 1 : 0;
+    }
+    return below;
+}
+
 // Per-transform constants derived at compile time.
 template <int ID>
 struct Tf {
@@ -166,6 +186,26 @@ struct Tf {
     }
     static constexpr Tables kTab = make_tables();
     static constexpr int32_t mu(int k, int l) { return kTab.mu[8 * k + l]; }
+    struct NTab {
+        int32_t n[8];
+    };
+    static constexpr NTab make_n() {
+        NTab t{};
+        for (int k = 0; k < 8; ++k) t.n[k] = n(k);
+        return t;
+    }
+    static constexpr NTab kN = make_n();
+    struct ClsTab {
+        int32_t c[64];
+    };
+    static constexpr ClsTab make_cls() {
+        ClsTab t{};
+        for (int i = 0; i < 64; ++i) t.c[i] = class_of(kN.n, i >> 3, i & 7);
+        return t;
+    }
+    static constexpr ClsTab kCls = make_cls();
+    // scale class of (k, l), a table filled at compile time
+    static constexpr int cls(int k, int l) { return kCls.c[8 * k + l]; }
     static constexpr double skl(int k, int l) { return kTab.skl[8 * k + l]; }
     static constexpr int32_t L() { return L1() * L1(); }
     // |Y| fits int16 for 8-bit input (checked by the host bound routine too).
@@ -234,14 +274,14 @@ struct CodecArgs {
     int32_t wpf_s;
 };
 
-// Quantiser constants of the built-in codec kernels per zig-zag position z
-// (a second kernel argument; zero when there is no quantiser), with
-// d = step mu for a class n_k n_l = mu^2.
+// Quantiser constants of the built-in codec kernels per scale class (a second
+// kernel argument; zero when there is no quantiser), with d = step mu for a
+// class n_k n_l = mu^2.
 struct QuantTables {
-    float qc1[64];       // 1 / d                       (rational classes)
-    float qc2[64];       // (d + 1/2) / (2 d)           (rational classes)
-    double qinv[64];     // s_k s_l / step              (irrational classes)
-    double qdeq[64];     // step s_k s_l: dequantised B = q qdeq
+    float qc1[kMaxClasses];       // 1 / d                       (rational classes)
+    float qc2[kMaxClasses];       // (d + 1/2) / (2 d)           (rational classes)
+    double qinv[kMaxClasses];     // s_k s_l / step              (irrational classes)
+    double qdeq[kMaxClasses];     // step s_k s_l: dequantised B = q qdeq
 };
 
 struct DctArgs {

@@ -280,9 +280,9 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const QuantTabl
             int v = Y[k][l];
             if constexpr (QUANT) {
                 if (Tf<ID>::mu(k, l) != 0)
-                    v = quant_rational_f(v, qt.qc1[z], qt.qc2[z]);
+                    v = quant_rational_f(v, qt.qc1[Tf<ID>::cls(k, l)], qt.qc2[Tf<ID>::cls(k, l)]);
                 else
-                    v = rne_i32(double(v) * qt.qinv[z]);   // never a half: see quant_irrational
+                    v = rne_i32(double(v) * qt.qinv[Tf<ID>::cls(k, l)]);   // never a half: see quant_irrational
             }
             C[k][l] = (z < a.r) ? v : 0;
         }
@@ -349,7 +349,7 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const QuantTabl
             for (int l = 0; l < KB; ++l)
                 // q step is exact in float64 (|q| < 2^15, step < 2^16) and needs no
                 // quarter-rate 32-bit integer multiply
-                Yd[k][l] = (k + l <= BAND) ? double(C[k][l]) * qt.qdeq[zz_pos(k, l)] : 0.0;
+                Yd[k][l] = (k + l <= BAND) ? double(C[k][l]) * qt.qdeq[Tf<ID>::cls(k, l)] : 0.0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             double yin0[8], yin1[8];
@@ -386,9 +386,9 @@ __device__ __forceinline__ void process_tile(const CodecArgs &a, const QuantTabl
                 inv8<ID, KB>(half ? yin1 : yin0, xo);
                 int q[8];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) q[m] = clamp255(rne_i32(xo[m]));
-                const u32x2 v = emit_row(q, MODE == kEvaluate ? pix[xr][0] : 0u,
-                                         MODE == kEvaluate ? pix[xr][1] : 0u, sq, cross);
+                for (int m = 0; m < 8; ++m) q[m] = rne_i32(xo[m]);
+                const u32x2 v = emit_row_sat(q, MODE == kEvaluate ? pix[xr][0] : 0u,
+                                             MODE == kEvaluate ? pix[xr][1] : 0u, sq, cross);
                 if (active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + xr * P.pitch_out));
             }
         }

@@ -123,6 +123,35 @@ __device__ __forceinline__ void load_tile(const CodecArgs &a, const Tile &t, uin
     }
 }
 
+// Two int16 halves of x saturated to [0, 255] and packed as bytes 0 and 1 (the
+// upper half of the result is zero).
+__device__ __forceinline__ uint32_t sat_pk_u8_i16(uint32_t x) {
+    uint32_t r;
+    asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// As emit_row, for a row of rounded values that still need clipping to
+// [0, 255] (|q| < 2^15): pairs of values as int16 halves, one saturating pack
+// per pair, two pairs per word.
+__device__ __forceinline__ u32x2 emit_row_sat(const int (&q)[8], uint32_t w0, uint32_t w1,
+                                              uint32_t &sq, uint32_t &cross) {
+    uint32_t b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        b[i] = sat_pk_u8_i16(__builtin_amdgcn_perm(uint32_t(q[2 * i + 1]), uint32_t(q[2 * i]), 0x05040100u));
+    u32x2 out;
+    out.x = b[0] | (b[1] << 16);
+    out.y = b[2] | (b[3] << 16);
+    sq = __builtin_amdgcn_udot4(out.x, out.x, sq, false);
+    sq = __builtin_amdgcn_udot4(out.y, out.y, sq, false);
+    sq = __builtin_amdgcn_udot4(w0, w0, sq, false);
+    sq = __builtin_amdgcn_udot4(w1, w1, sq, false);
+    cross = __builtin_amdgcn_udot4(out.x, w0, cross, false);
+    cross = __builtin_amdgcn_udot4(out.y, w1, cross, false);
+    return out;
+}
+
 // Pack a reconstructed row (q in [0, 255]) into bytes and accumulate the two
 // dot-product sums whose combination is the squared error:
 // sum (q - a)^2 = [sum q^2 + sum a^2] - 2 sum q a.

@@ -185,21 +185,17 @@ __device__ __forceinline__ void process_dtile(const DctArgs &a, const DTile &T, 
     }
     if constexpr (MODE == kEncode) return;
 
-    // ---- round, clip, store 4 pixels per pixel tile, squared error.  Clamping
-    // to [0, 255] first and adding 1.5 * 2^23 leaves round-half-to-even of the
-    // value in the low byte of the float's bits.
+    // ---- round, clip, store 4 pixels per pixel tile, squared error: one
+    // v_cvt_pk_u8_f32 per pixel rounds half to even, saturates to [0, 255] and
+    // places the byte.
     uint32_t sq = 0, cross = 0;
     uint8_t *dbase = a.out ? a.out + int64_t(T.f) * a.fs_out + P.out_off : nullptr;   // wave-uniform
     const uint32_t doff = T.out_off + __umul24(uint32_t(g >> 1), uint32_t(P.pitch_out)) + 4u * uint32_t(g & 1);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        uint32_t v[4];
+        uint32_t word = __builtin_amdgcn_cvt_pk_u8_f32(acc[t][0], 0u, 0u);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            v[i] = __float_as_uint(__builtin_amdgcn_fmed3f(acc[t][i], 0.f, 255.f) + 12582912.0f);
-        const uint32_t lo = __builtin_amdgcn_perm(v[1], v[0], 0x0c0c0400u);   // bytes v0.b0, v1.b0
-        const uint32_t hi = __builtin_amdgcn_perm(v[3], v[2], 0x04000c0cu);   // bytes v2.b0, v3.b0 at 2, 3
-        const uint32_t word = lo | hi;
+        for (int i = 1; i < 4; ++i) word = __builtin_amdgcn_cvt_pk_u8_f32(acc[t][i], uint32_t(i), word);
         if (T.active && dbase)
             __builtin_nontemporal_store(word, (uint32_t *)(dbase + (doff + 2u * uint32_t(t) * uint32_t(P.pitch_out))));
         if constexpr (MODE == kEvaluate) {
@@ -456,16 +452,15 @@ __device__ __forceinline__ uint32_t process_rows(const DctArgs &a, const DTile &
             if constexpr (MODE == kDecode) acc[t] = mma16(K.i[s][t], blo, acc[t]);
         }
     }
-    // round (clamp, then 1.5 * 2^23 leaves the rounded value in the low byte),
-    // store the two rows, squared error
+    // round half to even with saturation to [0, 255], packed into byte i of the
+    // word (one v_cvt_pk_u8_f32 per pixel), store the two rows, squared error
     uint32_t w[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        uint32_t v[4];
+        uint32_t v = __builtin_amdgcn_cvt_pk_u8_f32(acc[t][0], 0u, 0u);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            v[i] = __float_as_uint(__builtin_amdgcn_fmed3f(acc[t][i], 0.f, 255.f) + 12582912.0f);
-        w[t] = __builtin_amdgcn_perm(v[1], v[0], 0x0c0c0400u) | __builtin_amdgcn_perm(v[3], v[2], 0x04000c0cu);
+        for (int i = 1; i < 4; ++i) v = __builtin_amdgcn_cvt_pk_u8_f32(acc[t][i], uint32_t(i), v);
+        w[t] = v;
     }
     uint8_t *dbase = a.out ? a.out + int64_t(T.f) * a.fs_out + P.out_off : nullptr;   // wave-uniform
     if (T.active && dbase) {
