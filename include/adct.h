@@ -385,12 +385,20 @@ adct_status adct_evaluate_batch(const uint8_t *base, const adct_plane *images, i
                                 int r_hi, uint64_t *sse, int wgs_per_cu, int split,
                                 adct_stream_t stream);
 
-/* A prepared sweep: the same computation captured once in a HIP graph (zero
- * fill + persistent sweep) with its schedule picked by timing every candidate
- * (wgs_per_cu, split) on the given input when autotune != 0 (this runs the
- * sweep several times on `stream` and synchronises it).  All pointers are baked
- * into the graph: the buffers must outlive the plan.  Launching replays the
- * graph on any stream. */
+/* A prepared sweep: the same computation with its schedule picked by timing
+ * every candidate (wgs_per_cu, split, and the DCT kernel's workgroups per CU)
+ * on the given input when autotune != 0 (this runs the sweep several times on
+ * `stream` and synchronises it).  The plan owns a second stream, two events and
+ * two device work counters (8 bytes); when the list holds both the DCT and
+ * integer transforms, a launch runs the DCT kernel on that second stream beside
+ * the integer kernel on `stream` (forked after the zero fill, joined back into
+ * `stream` before the call's work counts as done), and both kernels take their
+ * items from the counters.  Launches of one plan are ordered by `stream`: two
+ * launches of the same plan that overlap on the device (on different streams)
+ * race on its counters and on sse.  The call is capturable into a HIP graph.
+ * All pointers are kept: the buffers must outlive the plan.  Destroying the
+ * plan waits for its second stream; the caller's stream must have finished
+ * the plan's launches. */
 typedef struct adct_batch_plan_s *adct_batch_plan;
 adct_status adct_batch_plan_create(const uint8_t *base, const adct_plane *images, int n_images,
                                    const adct_transform_id *transforms, int n_transforms, int r_lo,

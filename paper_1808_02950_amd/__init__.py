@@ -571,7 +571,8 @@ def evaluate_batch(base, images, transforms, r_lo: int = 1, r_hi: int = 63, sse=
 
 
 class BatchPlan:
-    """adct_batch_plan_*: the sweep captured in a HIP graph (optionally autotuned).
+    """adct_batch_plan_*: the sweep with a tuned schedule (optionally autotuned);
+    a launch runs the DCT and integer kernels side by side on two streams.
     Keeps references to the buffers it was built on."""
 
     def __init__(self, base, images, transforms, r_lo: int = 1, r_hi: int = 63, sse=None,

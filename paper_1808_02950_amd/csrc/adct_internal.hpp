@@ -235,6 +235,14 @@ struct PlaneArg {
     int32_t nbx_s;      //   (nbx_s < 0: nbx == 1)
 };
 
+// Two int16 halves of x saturated to [0, 255] and packed as bytes 0 and 1 (the
+// upper half of the result is zero).
+__device__ __forceinline__ uint32_t sat_pk_u8_i16(uint32_t x) {
+    uint32_t r;
+    asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Exact division of 0 <= n < 2^31 by a wave-uniform divisor d through a
 // multiply-high and a shift (Granlund-Montgomery with a 32-bit multiplier):
 // with l = ceil(log2 d), m = ceil(2^(31 + l) / d) < 2^32 and n / d =

@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -45,6 +46,7 @@ struct BatchImg {
 struct BatchArgs {
     const uint8_t *base;
     unsigned long long *sse;          // [image][transform][r - r_lo]
+    unsigned *ctr;                    // [2] work counters (integer, DCT) or null: grid stride
     int32_t n_images;
     int32_t n_transforms;
     int32_t r_lo, r_hi;
@@ -114,6 +116,22 @@ __device__ __forceinline__ void score_row(const int (&q)[8], uint32_t w0, uint32
     const uint32_t r67 = uint32_t(q[6]) | (uint32_t(q[7]) << 16);
     const uint32_t lo = __builtin_amdgcn_perm(r23, r01, 0x06040200u);
     const uint32_t hi = __builtin_amdgcn_perm(r67, r45, 0x06040200u);
+    sq = __builtin_amdgcn_udot4(lo, lo, sq, false);
+    sq = __builtin_amdgcn_udot4(hi, hi, sq, false);
+    cross = __builtin_amdgcn_udot4(lo, w0, cross, false);
+    cross = __builtin_amdgcn_udot4(hi, w1, cross, false);
+}
+
+// As score_row for a row of rounded values that still need clipping to
+// [0, 255] (|q| < 2^15): pairs as int16 halves, one saturating pack per pair.
+__device__ __forceinline__ void score_row_sat(const int (&q)[8], uint32_t w0, uint32_t w1, uint32_t &sq,
+                                              uint32_t &cross) {
+    uint32_t b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        b[i] = sat_pk_u8_i16(__builtin_amdgcn_perm(uint32_t(q[2 * i + 1]), uint32_t(q[2 * i]), 0x05040100u));
+    const uint32_t lo = b[0] | (b[1] << 16);
+    const uint32_t hi = b[2] | (b[3] << 16);
     sq = __builtin_amdgcn_udot4(lo, lo, sq, false);
     sq = __builtin_amdgcn_udot4(hi, hi, sq, false);
     cross = __builtin_amdgcn_udot4(lo, w0, cross, false);
@@ -271,66 +289,60 @@ static_assert(int_sweep_ranges_ok<ADCT_T1>() && int_sweep_ranges_ok<ADCT_T2>() &
                   int_sweep_ranges_ok<ADCT_RDCT>() && int_sweep_ranges_ok<ADCT_T4>(),
               "integer sweep ranges");
 
-// Exact round-half-to-even(n / L) clipped to [0, 255] without a 32-bit
-// multiply.  With c = clip(n) and u = 2c + L, the half-up quotient is
-// q = floor(u / 2L), found in float:
-//  * small L: u / 2L = c / L + 1/2 and fma(c, 1/L, 1/2 + 1/(4L)) lies in
-//    [q, q + 1): the fractions of u / 2L are multiples of 1/(2L), and the
-//    rounding error (below 256 * 2^-23 + 2^-24) is under the 1/(4L) offset;
-//  * large L: write 2L = 2^a b with b odd; q = floor(v / b) for
-//    v = u >> a = (c + L/2) >> (a - 1), and fma(v, 1/b, 1/(2b)) lies in
-//    [q, q + 1) by the same argument with spacing 1/b.
-// At a tie u = 2L q, i.e. c + L/2 - L q = 0 (L is even); that remainder is an
-// integer in [0, L), so minus one it is negative exactly at a tie, where an odd
-// q loses its low bit.
+// Exact round-half-to-even(n / L) without a 32-bit multiply or a clip.  The
+// sweep keeps P = n + L/2, so the half-up quotient is q = floor(P / L), found
+// in float: write L = 2^s d (s = 0 for small L, else the power of two of L, so
+// d is odd); floor(P / L) = floor(v / d) for v = P >> s, whose fractions are
+// multiples of 1/d, and fma(v, 1/d, 1/(2d)) = (v + 1/2) fl(1/d) rounded lies
+// within (257.5 * 2^-24 + 2^-16) < 1/(2d) of v/d + 1/(2d) while v/d <= 257,
+// so truncating it gives q.  Above that the float is still monotone in P and
+// every such q saturates to 255; for P < 0 the truncation is at most 0, which
+// saturates to 0.  At a tie P = L q exactly: the remainder x = P - L q is zero
+// there and in [1, L) elsewhere (a wrong q below 0 or above 256 makes x
+// negative or at least L, and leaves no tie to fix), so min(x, 1) is 0 exactly
+// at a tie, where an odd q loses its low bit.  The result, in [-2042, 2042],
+// is clipped by the saturating byte pack of score_row_sat.
 template <int ID>
 struct IntRound {
     static constexpr int32_t L = Tf<ID>::L();
-    static constexpr bool kShift = L >= 4096;
-    static constexpr int32_t a() {
+    static constexpr int32_t v2() {
         int32_t s = 0;
-        while (((2 * L) >> s & 1) == 0) ++s;
+        while ((L >> s & 1) == 0) ++s;
         return s;
     }
-    static constexpr int32_t kA = kShift ? a() : 0;
-    static constexpr int32_t kB = (2 * L) >> kA;           // odd part of 2L (large L)
-    static_assert(!kShift || (kA >= 1 && kB <= 8192), "divisor too large for the float quotient");
-    static_assert(kShift || L <= 8192, "small-L path needs 1/(4L) above the rounding error");
-    static_assert(int64_t(256) * L < (int64_t(1) << (24 + kA)), "quotient input must be exact in float");
-    static_assert(L % 2 == 0, "the tie test halves u");
+    static constexpr int32_t kS = L >= 4096 ? v2() : 0;
+    static constexpr int32_t kD = L >> kS;               // divisor of the float quotient
+    static_assert(kD < 16000, "divisor too large for the float quotient");
+    static_assert(L % 2 == 0, "the sweep adds L/2");
 };
 
-// wave-uniform constants of the rounding, held in scalar registers (a VOP3
+// wave-uniform constant of the rounding, held in a scalar register (a VOP3
 // instruction takes no 32-bit literal on this target)
 struct IntRoundRegs {
-    int32_t hLm1, mL;     // L/2 - 1, -L
+    int32_t mL;           // -L
 };
 
 template <int ID>
 __device__ __forceinline__ IntRoundRegs int_round_regs() {
     IntRoundRegs r;
-    asm("s_mov_b32 %0, %1" : "=s"(r.hLm1) : "i"(IntRound<ID>::L / 2 - 1));
     asm("s_mov_b32 %0, %1" : "=s"(r.mL) : "i"(-IntRound<ID>::L));
     return r;
 }
 
+// P = n + L/2 -> round-half-to-even(n / L), unclipped
 template <int ID>
-__device__ __forceinline__ int rne_clip_int(int n, const IntRoundRegs &c) {
+__device__ __forceinline__ int rne_int(int P, const IntRoundRegs &c) {
     using R = IntRound<ID>;
-    const int nc = min(max(n, 0), 255 * R::L);
-    float f;
-    if constexpr (R::kShift) {
-        constexpr float kInv = 1.0f / float(R::kB);
-        constexpr float kOff = 0.5f / float(R::kB);
-        f = __builtin_fmaf(float(uint32_t(nc + R::L / 2) >> (R::kA - 1)), kInv, kOff);
-    } else {
-        constexpr float kInv = 1.0f / float(R::L);
-        constexpr float kOff = 0.5f + 0.25f / float(R::L);
-        f = __builtin_fmaf(float(nc), kInv, kOff);
-    }
-    const uint32_t q = uint32_t(f);
-    const uint32_t tie = uint32_t(nc + c.hLm1 + __mul24(int(q), c.mL)) >> 31;
-    return int(q & ~tie);
+    constexpr float kInv = 1.0f / float(R::kD);
+    constexpr float kOff = 0.5f / float(R::kD);
+    const float f = __builtin_fmaf(float(R::kS ? (P >> R::kS) : P), kInv, kOff);
+    const int q = int(f);
+    const uint32_t x = uint32_t(__mul24(q, c.mL) + P);
+    // min(x, 1) as one instruction (left to itself the compiler turns the
+    // comparison with zero into a compare and a select)
+    uint32_t m;
+    asm("v_min_u32 %0, 1, %1" : "=v"(m) : "v"(x));
+    return q & int(m | ~1u);
 }
 
 // Per-wave coefficient staging for the integer sweep: [z][lane] int16.
@@ -389,11 +401,11 @@ __device__ __forceinline__ void sweep_int(const uint32_t (&pix_in)[8][2], bool a
         fwd_cols16<ID>(Z, lds, lane, std::make_index_sequence<8>{});
     }
     __builtin_amdgcn_wave_barrier();
-    int A[8][8];
+    int A[8][8];      // n + L/2: the reconstruction numerator, biased for rne_int
 #pragma unroll
     for (int x = 0; x < 8; ++x)
 #pragma unroll
-        for (int y = 0; y < 8; ++y) A[x][y] = 0;
+        for (int y = 0; y < 8; ++y) A[x][y] = IntRound<ID>::L / 2;
     const uint32_t e_pix = pix_energy(pix);
     const StepEnt *S = kStepDev[ID].s;
     const IntRoundRegs rc = int_round_regs<ID>();
@@ -414,8 +426,8 @@ __device__ __forceinline__ void sweep_int(const uint32_t (&pix_in)[8][2], bool a
         for (int x = 0; x < 8; ++x) {
             int q[8];
 #pragma unroll
-            for (int y = 0; y < 8; ++y) q[y] = rne_clip_int<ID>(A[x][y], rc);
-            score_row(q, pix[x][0], pix[x][1], sq, cross);
+            for (int y = 0; y < 8; ++y) q[y] = rne_int<ID>(A[x][y], rc);
+            score_row_sat(q, pix[x][0], pix[x][1], sq, cross);
         }
         unsigned err = sq - 2u * cross;
         if (j + 1 >= r_lo) {
@@ -618,13 +630,26 @@ __device__ __forceinline__ void load_tile(const BatchArgs &a, int tile, int lane
     }
 }
 
+// The item a single-wave workgroup takes after `it`: the next one of its grid
+// stride, or, with a work counter, the next one nobody has taken (workgroup b
+// starts with item b, so the counter numbers the items from gridDim.x on).
+// The counter balances the two kernels when they share the chip: a workgroup
+// that becomes resident late takes only what is left.
+__device__ __forceinline__ int next_item(unsigned *ctr, int it) {
+    if (!ctr) return it + int(gridDim.x);
+    unsigned v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(ctr, 1u);
+    return int(gridDim.x) + __builtin_amdgcn_readfirstlane(int(__builtin_amdgcn_readlane(int(v), 0)));
+}
+
 // integer transforms: items are (tile, group) with group g taking the integer
 // transforms g, g + split, ... of the list
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_int(const BatchArgs a) {
     const int lane = threadIdx.x;
     const int items = a.total_tiles * a.split;
     const int nr = a.r_hi - a.r_lo + 1;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    unsigned *ctr = a.ctr ? a.ctr + 0 : nullptr;
+    for (int it = blockIdx.x; it < items; it = next_item(ctr, it)) {
         const int tile = it / a.split, grp = it - tile * a.split;
         TileRef T;
         load_tile(a, tile, lane, T);
@@ -648,7 +673,8 @@ __global__ __launch_bounds__(64) void k_batch_dct(const BatchArgs a) {
     const int lane = threadIdx.x;
     const int items = a.total_tiles * a.n_dct;
     const int nr = a.r_hi - a.r_lo + 1;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    unsigned *ctr = a.ctr ? a.ctr + 1 : nullptr;
+    for (int it = blockIdx.x; it < items; it = next_item(ctr, it)) {
         const int tile = it / a.n_dct, d = it - tile * a.n_dct;
         TileRef T;
         load_tile(a, tile, lane, T);
@@ -657,9 +683,10 @@ __global__ __launch_bounds__(64) void k_batch_dct(const BatchArgs a) {
     }
 }
 
-__global__ void k_zero(unsigned long long *p, int64_t n) {
+__global__ void k_zero(unsigned long long *p, int64_t n, unsigned *ctr) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
+    if (ctr && i < 2) ctr[i] = 0u;
 }
 
 int device_cus() {
@@ -676,20 +703,32 @@ int device_cus() {
 // zero fill, then the DCT kernel (if the list has the DCT), then the integer
 // kernel (if it has integer transforms).  wgs_per_cu sets the integer kernel's
 // resident single-wave workgroups per compute unit; the DCT kernel fills every
-// slot its 32 KB of LDS allows.
-adct_status enqueue(const BatchArgs &a, int wgs_per_cu, hipStream_t s) {
+// slot its LDS and registers allow, or at most dct_per_cu per CU if that is set.  With a second stream s2 (and two events) the
+// DCT kernel runs on s2 beside the integer kernel: s2 waits for the zero fill,
+// s waits for the DCT kernel before it returns (a fork and a join, which stream
+// capture records as two graph branches).
+adct_status enqueue(const BatchArgs &a, int wgs_per_cu, hipStream_t s, hipStream_t s2 = nullptr,
+                    hipEvent_t fork = nullptr, hipEvent_t join = nullptr, int dct_per_cu = 0) {
     const int64_t n = int64_t(a.n_images) * a.n_transforms * (a.r_hi - a.r_lo + 1);
-    hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a.sse, n);
+    hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a.sse, n, a.ctr);
     ADCT_HIP(hipGetLastError());
     const int cus = device_cus();
     if (cus <= 0) return fail(ADCT_EDEVICE, "cannot query the device");
+    const bool branches = s2 && fork && join && a.n_dct > 0 && a.n_int > 0;
+    hipStream_t sd = s;
+    if (branches) {
+        ADCT_HIP(hipEventRecord(fork, s));
+        ADCT_HIP(hipStreamWaitEvent(s2, fork, 0));
+        sd = s2;
+    }
     if (a.n_dct > 0) {
         int per_cu = 0;
         ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_dct, 64, 0));
         if (per_cu < 1) per_cu = 1;
+        if (dct_per_cu > 0) per_cu = std::min(per_cu, dct_per_cu);
         const int64_t items = int64_t(a.total_tiles) * a.n_dct;
         const int grid = int(std::max<int64_t>(1, std::min<int64_t>(items, int64_t(per_cu) * cus)));
-        hipLaunchKernelGGL(k_batch_dct, dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_batch_dct, dim3(grid), dim3(64), 0, sd, a);
         ADCT_HIP(hipGetLastError());
     }
     if (a.n_int > 0) {
@@ -698,20 +737,49 @@ adct_status enqueue(const BatchArgs &a, int wgs_per_cu, hipStream_t s) {
         hipLaunchKernelGGL(k_batch_int, dim3(grid), dim3(64), 0, s, a);
         ADCT_HIP(hipGetLastError());
     }
+    if (branches) {
+        ADCT_HIP(hipEventRecord(join, s2));
+        ADCT_HIP(hipStreamWaitEvent(s, join, 0));
+    }
     return ADCT_OK;
 }
+
+// a second stream (default priority) and the fork / join events of a plan
+struct Branch {
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    adct_status make() {
+        ADCT_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        ADCT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        ADCT_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        return ADCT_OK;
+    }
+    ~Branch() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s2) (void)hipStreamDestroy(s2);
+    }
+};
 
 }  // namespace
 }  // namespace adct
 
 using namespace adct;
 
+// A plan is the argument block, its tuned schedule, the two work counters and
+// the second stream with its fork / join events.  Launching enqueues the
+// schedule; the mutex keeps two host threads from interleaving the event
+// records of one plan.
 struct adct_batch_plan_s {
     BatchArgs args;
     int wgs_per_cu = 4;
+    int dct_per_cu = 0;
     double tuned_ms = 0.0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    Branch br;
+    std::mutex mu;
+    ~adct_batch_plan_s() {
+        if (args.ctr) (void)hipFree(args.ctr);
+    }
 };
 
 namespace {
@@ -790,6 +858,16 @@ adct_status adct_batch_plan_create(const uint8_t *base, const adct_plane *images
         return st;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Branch &br = p->br;
+    if (adct_status stb = br.make()) {
+        delete p;
+        return stb;
+    }
+    if (hipMalloc(&p->args.ctr, 2 * sizeof(unsigned)) != hipSuccess) {
+        p->args.ctr = nullptr;
+        delete p;
+        return fail(ADCT_EDEVICE, "cannot allocate the work counters");
+    }
     if (autotune) {
         // time every (workgroups per CU, transform split) candidate on the real
         // input and keep the fastest
@@ -799,16 +877,19 @@ adct_status adct_batch_plan_create(const uint8_t *base, const adct_plane *images
             return fail(ADCT_EDEVICE, "hipEventCreate failed");
         }
         double best = 1e30;
-        int best_w = 4, best_s = 1;
+        int best_w = 4, best_s = 1, best_d = 0;
         const int n_split = std::max(p->args.n_int, 1);
+        const bool both = p->args.n_int > 0 && p->args.n_dct > 0;
         for (int split = 1; split <= n_split; ++split) {
             if (n_split % split) continue;
-            for (int w : {4, 6, 8, 12, 16}) {
+            for (int w : {4, 6, 8, 12, 16})
+            for (int d : {0, 4, 2}) {
+                if (d && !both) continue;
                 BatchArgs a = p->args;
                 a.split = split;
-                st = enqueue(a, w, s);                         // warm
+                st = enqueue(a, w, s, br.s2, br.fork, br.join, d);     // warm
                 if (!st) st = hipEventRecord(e0, s) == hipSuccess ? ADCT_OK : ADCT_EDEVICE;
-                if (!st) st = enqueue(a, w, s);
+                if (!st) st = enqueue(a, w, s, br.s2, br.fork, br.join, d);
                 if (!st) st = hipEventRecord(e1, s) == hipSuccess ? ADCT_OK : ADCT_EDEVICE;
                 float ms = 0.f;
                 if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -823,48 +904,25 @@ adct_status adct_batch_plan_create(const uint8_t *base, const adct_plane *images
                     best = ms;
                     best_w = w;
                     best_s = split;
+                    best_d = d;
                 }
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         p->wgs_per_cu = best_w;
+        p->dct_per_cu = best_d;
         p->args.split = best_s;
         p->tuned_ms = best;
-    }
-    // capture zero-fill + sweep into a graph on a private stream
-    hipStream_t cap;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
-        delete p;
-        return fail(ADCT_EDEVICE, "hipStreamCreate failed");
-    }
-    st = ADCT_OK;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        st = fail(ADCT_EDEVICE, "hipStreamBeginCapture failed");
-    if (!st) {
-        const adct_status st2 = enqueue(p->args, p->wgs_per_cu, cap);
-        const hipError_t e = hipStreamEndCapture(cap, &p->graph);
-        if (st2) st = st2;
-        else if (e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
-    }
-    if (!st) {
-        const hipError_t e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
-    }
-    (void)hipStreamDestroy(cap);
-    if (st) {
-        if (p->graph) (void)hipGraphDestroy(p->graph);
-        delete p;
-        return st;
     }
     *out = p;
     return ADCT_OK;
 }
-
 adct_status adct_batch_plan_launch(adct_batch_plan plan, adct_stream_t stream) {
     if (!plan) return fail(ADCT_EINVAL, "plan is null");
-    ADCT_HIP(hipGraphLaunch(plan->exec, reinterpret_cast<hipStream_t>(stream)));
-    return ADCT_OK;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    return enqueue(plan->args, plan->wgs_per_cu, reinterpret_cast<hipStream_t>(stream), plan->br.s2,
+                   plan->br.fork, plan->br.join, plan->dct_per_cu);
 }
 
 adct_status adct_batch_plan_info(adct_batch_plan plan, int *wgs_per_cu, int *split, double *tuned_ms) {
@@ -877,8 +935,8 @@ adct_status adct_batch_plan_info(adct_batch_plan plan, int *wgs_per_cu, int *spl
 
 adct_status adct_batch_plan_destroy(adct_batch_plan plan) {
     if (!plan) return ADCT_OK;
-    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    // the plan's kernels may still run on its second stream
+    (void)hipStreamSynchronize(plan->br.s2);
     delete plan;
     return ADCT_OK;
 }

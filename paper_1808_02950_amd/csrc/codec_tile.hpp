@@ -123,14 +123,6 @@ __device__ __forceinline__ void load_tile(const CodecArgs &a, const Tile &t, uin
     }
 }
 
-// Two int16 halves of x saturated to [0, 255] and packed as bytes 0 and 1 (the
-// upper half of the result is zero).
-__device__ __forceinline__ uint32_t sat_pk_u8_i16(uint32_t x) {
-    uint32_t r;
-    asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
 // As emit_row, for a row of rounded values that still need clipping to
 // [0, 255] (|q| < 2^15): pairs of values as int16 halves, one saturating pack
 // per pair, two pairs per word.

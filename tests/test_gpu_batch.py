@@ -1,5 +1,6 @@
-"""GPU rate-distortion sweep (one persistent launch, optionally replayed from a
-HIP graph) against the oracle's per-(image, transform, r) definition."""
+"""GPU rate-distortion sweep (persistent launches; a plan runs the DCT and
+integer kernels side by side on two streams) against the oracle's
+per-(image, transform, r) definition."""
 
 import numpy as np
 import pytest
@@ -75,7 +76,7 @@ def test_batch_lists_and_ranges(cuda, small_set, names, r_lo, r_hi):
     _check(sse, ref, names)
 
 
-def test_batch_graph_replays(cuda, small_set):
+def test_batch_plan_replays(cuda, small_set):
     import torch
     base, planes = _pack(small_set, cuda)
     names = ["DCT", "T1", "LO", "T6", "RDCT", "T4"]
@@ -90,6 +91,39 @@ def test_batch_graph_replays(cuda, small_set):
         got = plan.launch().clone()
         torch.cuda.synchronize()
         assert np.array_equal(got.cpu().numpy(), eager), rep
+    # back-to-back launches on a side stream, read after the stream alone is synchronised
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        plan.launch(stream=side)
+    side.synchronize()
+    assert np.array_equal(plan.sse.cpu().numpy(), eager)
+    plan.close()
+
+
+def test_batch_plan_in_captured_graph(cuda, small_set):
+    """A plan launch captured by the caller (the fork and join become two graph
+    branches): every replay, with eager work and synchronisation between
+    replays, equals the eager sweep."""
+    import torch
+    base, planes = _pack(small_set, cuda)
+    names = ["T1", "DCT", "LO"]
+    eager = A.evaluate_batch(base, planes, names, 2, 50).cpu().numpy()
+    plan = A.BatchPlan(base, planes, names, 2, 50, autotune=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    scratch = torch.empty(1 << 20, device=cuda)
+    for rep in range(4):
+        plan.sse.fill_(-1)
+        scratch.normal_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(plan.sse.cpu().numpy(), eager), rep
+    del g
     plan.close()
 
 
