@@ -377,7 +377,13 @@ struct WgradArgs {
     const uint8_t *x;      // decoded images (first layer)
     float *part;           // [workgroup][kParams]
     int H, W, lw, bands;   // W = 1 << lw
+    int items;             // (image, 16-row band) pairs; workgroup b takes b, b + grid, ...
 };
+
+// Workgroups of the weight-gradient kernels: each loops over its (image, band)
+// items in a fixed order and writes one partial row, so the partial sums the
+// reduction reads are at most this many rows whatever the batch.
+constexpr int kWgradGrid = 512;
 
 // rows [row0, row0 + nrows) of a 32-channel map -> T[slot * sstride + r * rpitch + coff + px]
 // (W = 1 << lw)
@@ -456,7 +462,6 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
     const int W = a.W, DS = dz_stride(W), AP = act_pitch(W), AS = act_stride(W);
     uint16_t *dzT = sm, *aT = sm + 32 * DS;
-    const int img = int(blockIdx.x) / a.bands, y0 = (int(blockIdx.x) % a.bands) * 16;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int oh = wave >> 1, ih = wave & 1;
@@ -468,6 +473,8 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     f32x4 accb = {0.f, 0.f, 0.f, 0.f};
     const uint4 ones = {kOne2, kOne2, kOne2, kOne2};
     const int lcpr = a.lw - 5;   // log2 of the 32-pixel chunks per row
+    for (int item = int(blockIdx.x); item < a.items; item += int(gridDim.x)) {
+    const int img = item / a.bands, y0 = (item % a.bands) * 16;
     // sub-band sb + 1 is loaded into registers while sub-band sb is computed
     Staged<4> sd;   // 4 rows x 4 chunks x W <= 1024 chunks
     Staged<6> sa;   // 6 rows
@@ -496,6 +503,8 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
             if (ih == 0) accb = mma32(A, ones, accb);
         }
     }
+    __syncthreads();   // the next item restages the tiles
+    }
     float *dst = a.part + int64_t(blockIdx.x) * kParams;
     const int ii = slot_channel(16 * ih + n);
 #pragma unroll
@@ -517,7 +526,6 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
     const int W = a.W, DS = kSb1 * W + 8, AP = act_pitch(W);
     uint16_t *dzT = sm, *xT = sm + 32 * DS;
-    const int img = int(blockIdx.x) / a.bands, y0 = (int(blockIdx.x) % a.bands) * 16;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int c = tid; c < (kSb1 + 2) * 16; c += 256) {
@@ -529,6 +537,8 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
     const int dy = tap / 3, dx = tap % 3;
     const int cpr = W / 32;
     // the next sub-band is loaded into registers while the current one is used
+    for (int item = int(blockIdx.x); item < a.items; item += int(gridDim.x)) {
+    const int img = item / a.bands, y0 = (item % a.bands) * 16;
     Staged<kSb1> sd;
     uint16_t xv[3];   // (kSb1 + 2) rows x W <= 640 values, 3 per thread
     auto load_x = [&](int r0) {
@@ -568,6 +578,7 @@ __global__ __launch_bounds__(256) void k_wgrad1(const WgradArgs a) {
         }
     }
     __syncthreads();
+    }
     float *red = reinterpret_cast<float *>(smem4);   // [32][10]
     for (int w = 0; w < 4; ++w) {
         if (wave == w && n < 10)
@@ -593,7 +604,6 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
     const int W = a.W, DS = kSb1 * W + 8, AP = act_pitch(W);
     uint16_t *aT = sm, *gT = sm + 32 * DS;
-    const int img = int(blockIdx.x) / a.bands, y0 = (int(blockIdx.x) % a.bands) * 16;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int c = tid; c < (kSb1 + 2) * 16; c += 256) {
@@ -604,6 +614,8 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
     const int tap = n < 9 ? n : 4;
     const int dy = tap / 3, dx = tap % 3;
     const int cpr = W / 32;
+    for (int item = int(blockIdx.x); item < a.items; item += int(gridDim.x)) {
+    const int img = item / a.bands, y0 = (item % a.bands) * 16;
     Staged<kSb1> sa;
     uint16_t gv[3];
     auto load_g = [&](int r0) {
@@ -641,6 +653,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
         }
     }
     __syncthreads();
+    }
     float *red = reinterpret_cast<float *>(smem4);   // [32 channels][9 taps]
     for (int w = 0; w < 4; ++w) {
         if (wave == w)
@@ -668,9 +681,27 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
 // then the loss) with all 256 threads and a fixed-order tree.
 constexpr int kRedCols = 16, kRedGroups = 16;
 constexpr int kRedParamBlocks = (kOffB3 + kRedCols - 1) / kRedCols;
+
+// Adam's state and hyper-parameters (c1, c2: the bias corrections of the step)
+struct AdamArgs {
+    float *p, *m, *v;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+__device__ __forceinline__ void adam_one(const AdamArgs &a, int i, float g) {
+    const float mm = a.b1 * a.m[i] + (1.f - a.b1) * g;
+    const float vv = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
+    a.m[i] = mm;
+    a.v[i] = vv;
+    a.p[i] -= a.lr * (mm * a.c1) / (sqrtf(vv * a.c2) + a.eps);
+}
+
+// ADAM: the thread that completes a gradient entry also applies the update
+template <bool ADAM>
 __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, int n_wg,
                                                 const float *__restrict__ part3, int n_w3, float inv_count,
-                                                float *__restrict__ grad, float *__restrict__ loss) {
+                                                float *__restrict__ grad, float *__restrict__ loss,
+                                                const AdamArgs ad) {
     __shared__ float sm[256];
     const int tid = threadIdx.x;
     if (int(blockIdx.x) >= kRedParamBlocks) {
@@ -684,8 +715,12 @@ __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, 
             __syncthreads();
         }
         if (tid == 0) {
-            if (k) grad[kOffB3] = sm[0];
-            else if (loss) *loss = sm[0] * inv_count;
+            if (k) {
+                grad[kOffB3] = sm[0];
+                if constexpr (ADAM) adam_one(ad, kOffB3, sm[0]);
+            } else if (loss) {
+                *loss = sm[0] * inv_count;
+            }
         }
         return;
     }
@@ -710,20 +745,13 @@ __global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, 
 #pragma unroll
         for (int k = 0; k < kRedGroups; ++k) t += sm[k * kRedCols + c];
         grad[p] = t;
+        if constexpr (ADAM) adam_one(ad, p, t);
     }
 }
 
-__global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
-                                              const float *__restrict__ grad, float lr, float b1, float b2,
-                                              float eps, float c1, float c2) {
+__global__ __launch_bounds__(256) void k_adam(const AdamArgs a, const float *__restrict__ grad) {
     const int i = int(blockIdx.x) * 256 + int(threadIdx.x);
-    if (i >= kParams) return;
-    const float g = grad[i];
-    const float mm = b1 * m[i] + (1.f - b1) * g;
-    const float vv = b2 * v[i] + (1.f - b2) * g * g;
-    m[i] = mm;
-    v[i] = vv;
-    p[i] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    if (i < kParams) adam_one(a, i, grad[i]);
 }
 
 // ---------------------------------------------------------------- fused inference
@@ -1049,7 +1077,7 @@ adct_status train_dims(int n, int H, int W) {
 WsLayout layout(int n, int H, int W) {
     WsLayout L;
     const int64_t px = int64_t(n) * H * W;
-    L.n_wg = n * (H / 16);
+    L.n_wg = std::min(n * (H / 16), kWgradGrid);
     L.n_w3 = n * (W / 16) * (H / kConvRows);
     int64_t o = 0;
     L.packed = o; o += up256(kPackBytes);
@@ -1071,8 +1099,27 @@ size_t wgrad_lds(int W) {
     return std::max(std::max(stage2, stage13), size_t(32 * 10) * 4);
 }
 
+// Adam's bias corrections for a step (host side, float64)
+adct_status adam_args(float *params, float *m, float *v, int step, float lr, float beta1, float beta2,
+                      float eps, AdamArgs *a) {
+    if (step < 1) return fail(ADCT_ERANGE, "step counts from 1");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(ADCT_ERANGE, "need lr >= 0, beta1 and beta2 in [0, 1), eps > 0");
+    a->p = params;
+    a->m = m;
+    a->v = v;
+    a->lr = lr;
+    a->b1 = beta1;
+    a->b2 = beta2;
+    a->eps = eps;
+    a->c1 = float(1.0 / (1.0 - std::pow(double(beta1), step)));
+    a->c2 = float(1.0 / (1.0 - std::pow(double(beta2), step)));
+    return ADCT_OK;
+}
+
+// adam: null for the gradient alone, else the update is applied by the reduction
 adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t *orig, int n, int H, int W,
-                        char *ws, float *grad, float *loss, float *y_out, hipStream_t s) {
+                        char *ws, float *grad, float *loss, float *y_out, const AdamArgs *adam, hipStream_t s) {
     const WsLayout L = layout(n, H, W);
     uint16_t *packed = reinterpret_cast<uint16_t *>(ws + L.packed);
     const float *bias = reinterpret_cast<const float *>(ws + L.packed + kPackBiasByte);
@@ -1112,6 +1159,7 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     wa.W = W;
     wa.lw = W == 64 ? 6 : 5;
     wa.bands = H / 16;
+    wa.items = n * wa.bands;
     const size_t lds = wgrad_lds(W);
     WgradArgs w3 = wa;
     w3.g = g3; w3.act = a2;
@@ -1122,21 +1170,22 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     WgradArgs w1 = wa;
     w1.g = dz1; w1.x = recon;
     hipLaunchKernelGGL(k_wgrad1, dim3(L.n_wg), blk, lds, s, w1);
-    hipLaunchKernelGGL(k_reduce, dim3(kRedParamBlocks + 2), blk, 0, s, part, L.n_wg, part3, L.n_w3,
-                       float(1.0 / (double(n) * H * W)), grad, loss);
+    const float inv_count = float(1.0 / (double(n) * H * W));
+    if (adam)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(kRedParamBlocks + 2), blk, 0, s, part, L.n_wg, part3, L.n_w3,
+                           inv_count, grad, loss, *adam);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3(kRedParamBlocks + 2), blk, 0, s, part, L.n_wg, part3, L.n_w3,
+                           inv_count, grad, loss, AdamArgs{});
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }
 
 adct_status launch_adam(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
                         float beta2, float eps, hipStream_t s) {
-    if (step < 1) return fail(ADCT_ERANGE, "step counts from 1");
-    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
-        return fail(ADCT_ERANGE, "need lr >= 0, beta1 and beta2 in [0, 1), eps > 0");
-    const double c1 = 1.0 / (1.0 - std::pow(double(beta1), step));
-    const double c2 = 1.0 / (1.0 - std::pow(double(beta2), step));
-    hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, params, m, v, grad, lr, beta1, beta2,
-                       eps, float(c1), float(c2));
+    AdamArgs ad;
+    if (adct_status st = adam_args(params, m, v, step, lr, beta1, beta2, eps, &ad)) return st;
+    hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, ad, grad);
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
 }
@@ -1217,7 +1266,7 @@ adct_status adct_filter_grad(const float *params, const uint8_t *recon, const ui
         return fail(ADCT_EINVAL, "params, recon, orig, workspace and grad are required");
     if (adct_status st = train_dims(n, H, W)) return st;
     if (ws_bytes < layout(n, H, W).total) return fail(ADCT_ECAP, "workspace too small");
-    return launch_grad(params, recon, orig, n, H, W, static_cast<char *>(workspace), grad, loss, y_out,
+    return launch_grad(params, recon, orig, n, H, W, static_cast<char *>(workspace), grad, loss, y_out, nullptr,
                        reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -1235,12 +1284,12 @@ adct_status adct_filter_train_step(float *params, float *m, float *v, int step, 
     if (adct_status st = train_dims(n, H, W)) return st;
     const WsLayout L = layout(n, H, W);
     if (ws_bytes < L.total) return fail(ADCT_ECAP, "workspace too small");
-    if (step < 1) return fail(ADCT_ERANGE, "step counts from 1");
+    AdamArgs ad;
+    if (adct_status st = adam_args(params, m, v, step, lr, beta1, beta2, eps, &ad)) return st;
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float *grad = reinterpret_cast<float *>(ws + L.grad);
-    if (adct_status st = launch_grad(params, recon, orig, n, H, W, ws, grad, loss, nullptr, s)) return st;
-    return launch_adam(params, m, v, grad, step, lr, beta1, beta2, eps, s);
+    return launch_grad(params, recon, orig, n, H, W, ws, grad, loss, nullptr, &ad, s);
 }
 
 adct_status adct_filter_apply(const void *packed, const uint8_t *frames, int64_t frame_stride, int n_frames,
