@@ -308,7 +308,7 @@ def search_wider_row():
 
 
 def batch_row():
-    """The 45-image rate-distortion sweep as one autotuned graph replay."""
+    """The 45-image rate-distortion sweep as one autotuned plan launch."""
     import numpy as np
     import torch
 
