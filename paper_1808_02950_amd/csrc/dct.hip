@@ -528,8 +528,14 @@ __device__ __forceinline__ void process_group(const DctArgs &a, const DGroup &G,
     }
 }
 
+// Held to 128 registers (4 waves per SIMD): left to itself the evaluate form
+// takes 152 (3 waves) for its two groups of tile state and pixels in flight.
+// The spills the cap costs (a few VGPRs to scratch, SGPRs to VGPR lanes) are
+// cheaper than the lost wave: 1.78 ms against 1.97-2.10 ms on the 300-frame
+// 4K stream, where 3 tiles per group at 4 waves took 1.87 ms and 2 tiles
+// 2.28 ms.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_dct_bf16(const DctArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dct_bf16(const DctArgs a) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int total = a.n_frames * a.waves_per_frame;
