@@ -116,11 +116,21 @@ adct_status adct_transform_bounds(adct_transform_id id, const adct_matrix *custo
 
 /* Host-only validation: the status the codec entry points would return for
  * this transform, retained count r and quantiser step (want_int16: whether
- * int16 coefficients are requested).  Quantiser steps are accepted only when
- * the dequantised reconstruction can never sit exactly on a half (for every
- * class n_k n_l = mu^2, step / mu must have an odd reduced denominator: a
- * multiple of 8 for T1, T2, T6, RDCT, T4, of 32 for LO); otherwise
- * ADCT_ENOTSUP. */
+ * int16 coefficients are requested).
+ *
+ * Quantiser steps and exact halves (Sec. 6.1.1 reconstruction, rounded half
+ * to even).  When for every class n_k n_l = mu^2 step / mu has an odd reduced
+ * denominator (a multiple of 8 for T1, T2, T6, RDCT, T4, of 32 for LO) no
+ * reconstruction can sit exactly on a half and the built-in kernels round in
+ * float64.  Any other step in [1, 65535] goes to the run-time-matrix kernels,
+ * which decide every pixel within their float64 error bound of a half by the
+ * exact sign of its distance in the field generated by the square roots of
+ * the row norms (sqrt 10 for T1 and T2, sqrt 3 for T4, sqrt 6 and sqrt 10 for
+ * T6, sqrt 2 and sqrt 3 for RDCT, sqrt 3 and sqrt 10 for LO).  ADCT_ENOTSUP if
+ * the norms of a custom matrix bring in more than two independent square
+ * roots (or p q > 1024); ADCT_ERANGE if the step is too large for the 52-bit
+ * components of that decision.  Such steps run at the run-time kernels' speed
+ * (one tile per wave, no persistent grid). */
 adct_status adct_check_codec_args(adct_transform_id t, const adct_matrix *custom, int r,
                                   int quant_step, int want_int16);
 

@@ -190,11 +190,158 @@ bool rt_words_fit(const adct_matrix &m, int64_t cmax) {
     return nmax < kRtMaxInvNum;
 }
 
+// Prime factorisation of 0 < v < 2^31 by trial division.
+struct Fact {
+    int n = 0;
+    int64_t p[16];
+    int e[16];
+};
+Fact factor(int64_t v) {
+    Fact f;
+    for (int64_t d = 2; d * d <= v; ++d) {
+        if (v % d) continue;
+        f.p[f.n] = d;
+        f.e[f.n] = 0;
+        while (v % d == 0) {
+            v /= d;
+            ++f.e[f.n];
+        }
+        ++f.n;
+    }
+    if (v > 1) {
+        f.p[f.n] = v;
+        f.e[f.n] = 1;
+        ++f.n;
+    }
+    return f;
+}
+
+// squarefree part of a b and the mu with a b = mu^2 r
+void split_square(const Fact &fa, const Fact &fb, int64_t *mu, int64_t *r) {
+    int64_t m = 1, q = 1;
+    int64_t ps[32];
+    int es[32], n = 0;
+    for (int i = 0; i < fa.n; ++i) { ps[n] = fa.p[i]; es[n++] = fa.e[i]; }
+    for (int i = 0; i < fb.n; ++i) {
+        int j = 0;
+        while (j < n && ps[j] != fb.p[i]) ++j;
+        if (j == n) { ps[n] = fb.p[i]; es[n++] = fb.e[i]; }
+        else es[j] += fb.e[i];
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < es[i] / 2; ++k) m *= ps[i];
+        if (es[i] & 1) q *= ps[i];
+    }
+    *mu = m;
+    *r = q;
+}
+
+int64_t squarefree(int64_t v) {
+    int64_t mu, r;
+    split_square(factor(v), Fact{}, &mu, &r);
+    return r;
+}
+
+// Tables of the exact near-half decision for matrix m, zig-zag band `band`
+// (coefficients k + l <= band) and a quantiser step: the squarefree parts of
+// n_k n_l, two generators, the common denominator and weights, and the word
+// bounds for any int16 levels a decoder may be handed.
+adct_status build_settle(const adct_matrix &m, int band, int step, RtSettle *st) {
+    memset(st, 0, sizeof(*st));
+    Fact fn[8];
+    for (int k = 0; k < 8; ++k) fn[k] = factor(m.n[k]);
+    int64_t mu[64], rr[64];
+    int64_t R[64];
+    int nr = 0;
+    for (int k = 0; k < 8; ++k)
+        for (int l = 0; l < 8; ++l) {
+            const int i = 8 * k + l;
+            split_square(fn[k], fn[l], &mu[i], &rr[i]);
+            if (k + l > band || rr[i] == 1) continue;
+            int j = 0;
+            while (j < nr && R[j] != rr[i]) ++j;
+            if (j == nr) R[nr++] = rr[i];
+        }
+    int64_t p = 1, q = 1, r3 = 1;
+    if (nr == 1) {
+        p = R[0];
+    } else if (nr > 1) {
+        bool found = false;
+        for (int i = 0; i < nr && !found; ++i)
+            for (int j = i + 1; j < nr && !found; ++j) {
+                const int64_t c = squarefree(R[i] * R[j]);
+                bool all = true;
+                for (int t = 0; t < nr; ++t) all &= R[t] == R[i] || R[t] == R[j] || R[t] == c;
+                if (all) {
+                    p = R[i];
+                    q = R[j];
+                    r3 = c;
+                    found = true;
+                }
+            }
+        if (!found)
+            return fail(ADCT_ENOTSUP, "quant_step admits exact half ties and the row norms bring in more than "
+                                      "two independent square roots: no exact decision of those halves");
+    }
+    if (p * q > kSettleMaxPQ) return fail(ADCT_ENOTSUP, "square roots of the row norms too large for the exact "
+                                                        "decision of half ties");
+    int64_t g = 1;
+    while (g * g * r3 < p * q) ++g;
+    int64_t D = 1;
+    for (int i = 0; i < 64; ++i) {
+        if ((i >> 3) + (i & 7) > band) continue;
+        D = lcm64(D, mu[i] * rr[i]);
+        if (D > (int64_t(1) << 40)) return fail(ADCT_ERANGE, "denominator of the exact half decision exceeds 2^40");
+    }
+    st->on = 1;
+    st->p = int32_t(p);
+    st->q = int32_t(q);
+    st->g = int32_t(g);
+    st->D = D;
+    int tmax = 0;
+    for (int i = 0; i < 64; ++i) tmax = std::max(tmax, std::abs(int(m.T[i])));
+    for (int i = 0; i < 64; ++i) {
+        const bool in = (i >> 3) + (i & 7) <= band;
+        st->w[i] = in ? int32_t(D / (mu[i] * rr[i])) : 0;
+        st->cls[i] = int8_t(rr[i] == 1 ? 0 : rr[i] == p ? 1 : rr[i] == q ? 2 : 3);
+    }
+    // every component of the sign test below 2^52 for |C| <= 32768, the pixel's
+    // floor in [-1, 255]
+    const __int128 cmax = 32768;
+    __int128 nmax[4] = {0, 0, 0, 0};
+    double sk = 0.0;
+    for (int x = 0; x < 8; ++x)
+        for (int y = 0; y < 8; ++y) {
+            __int128 nb[4] = {0, 0, 0, 0};
+            for (int k = 0; k < 8; ++k)
+                for (int l = 0; l < 8; ++l) {
+                    if (k + l > band) continue;
+                    nb[st->cls[8 * k + l]] += cmax * std::abs(m.T[8 * k + x] * m.T[8 * l + y]) * st->w[8 * k + l];
+                }
+            for (int c = 0; c < 4; ++c) nmax[c] = std::max(nmax[c], nb[c]);
+        }
+    for (int i = 0; i < 64; ++i)
+        if ((i >> 3) + (i & 7) <= band) sk += inv_sqrt_newton(int64_t(m.n[i >> 3]) * m.n[i & 7]);
+    const __int128 s2 = 2 * __int128(step), lim = kSettleMaxComp;
+    const __int128 comp[4] = {g * (s2 * nmax[0] + 513 * __int128(D)), g * s2 * nmax[1], g * s2 * nmax[2],
+                              s2 * nmax[3]};
+    for (int c = 0; c < 4; ++c)
+        if (comp[c] >= lim) return fail(ADCT_ERANGE, "quant_step too large for the exact decision of half ties");
+    // float64 error of a pixel below 20 2^-53 Tmax^2 step sum |C_kl| s_k s_l;
+    // the tolerance is 8 times that, and must stay below 1/4 for any int16 levels
+    st->tol_c = std::ldexp(1.0, -45) * double(tmax) * tmax * step;
+    if (st->tol_c * 32768.0 * sk >= 0.25)
+        return fail(ADCT_ERANGE, "quant_step too large for the exact decision of half ties");
+    return ADCT_OK;
+}
+
 struct Prepared {
     adct_matrix m;
     int band;
     bool quant;
-    bool runtime;      // the matrix goes to the run-time kernels (ADCT_CUSTOM)
+    bool runtime;      // the matrix goes to the run-time kernels (ADCT_CUSTOM, or a
+                       // quantiser step whose halves need the exact decision)
+    bool settle;       // the run-time kernels decide pixels near a half exactly
     RtMatArgs rt;
     QuantTables qt;    // built-in kernels' quantiser constants
 };
@@ -215,6 +362,27 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
     }
     out->band = r <= 10 ? 3 : 14;
     out->quant = quant_step > 0;
+    // A dequantised reconstruction sum_kl T T step q / sqrt(n_k n_l) can sit
+    // exactly on a half only through its rational part; that part has an odd
+    // denominator (so never a half) when every perfect-square class mu^2 =
+    // n_k n_l gives step / mu an odd reduced denominator.  Other steps go to the
+    // run-time kernels, which decide pixels near a half exactly.
+    out->settle = false;
+    if (out->quant) {
+        for (int k = 0; k < 8 && !out->settle; ++k)
+            for (int l = 0; l < 8; ++l) {
+                const int64_t prod = int64_t(out->m.n[k]) * out->m.n[l];
+                const int64_t mu = int64_t(llround(sqrt(double(prod))));
+                if (mu * mu != prod) continue;
+                int64_t g = mu, b = quant_step;
+                while (b) { const int64_t t2 = g % b; g = b; b = t2; }
+                if (((mu / g) & 1) == 0) {
+                    out->settle = true;
+                    break;
+                }
+            }
+        if (out->settle) out->runtime = true;
+    }
     const int64_t fb = fwd_bound(out->m);
     if (!out->quant) {
         if (need_int16_coef && fb > 32767)
@@ -229,25 +397,6 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
         return fail(ADCT_ERANGE, "custom matrix: |Y| bound too large for the float64 quantiser (>= 2^24)");
     }
     const int32_t *n = out->m.n;
-    if (out->quant) {
-        // The dequantised reconstruction sum_kl T T step q / sqrt(n_k n_l) can sit
-        // exactly on a half only through its rational part; that part has an odd
-        // denominator (so never a half) when every perfect-square class mu^2 =
-        // n_k n_l gives step / mu an odd reduced denominator.  Steps without
-        // this property are refused: float64 could not decide those halves.
-        for (int k = 0; k < 8; ++k)
-            for (int l = 0; l < 8; ++l) {
-                const int64_t prod = int64_t(n[k]) * n[l];
-                const int64_t mu = int64_t(llround(sqrt(double(prod))));
-                if (mu * mu != prod) continue;
-                int64_t g = mu, b = quant_step;
-                while (b) { const int64_t t2 = g % b; g = b; b = t2; }
-                if (((mu / g) & 1) == 0)
-                    return fail(ADCT_ENOTSUP, "quant_step admits exact half ties in the reconstruction "
-                                              "of this transform (step / sqrt(n_k n_l) must have an odd "
-                                              "reduced denominator for every rational class)");
-            }
-    }
     for (int k = 0; k < 8; ++k)
         for (int l = 0; l < 8; ++l) {
             const int64_t prod = int64_t(n[k]) * n[l];
@@ -281,6 +430,10 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
     if (out->runtime) {
         adct_status st = build_rt(out->m, &out->rt);
         if (st) return st;
+        if (out->settle) {
+            st = build_settle(out->m, out->band, quant_step, &out->rt.st);
+            if (st) return st;
+        }
     }
     a->step = quant_step;
     a->inv_step_f = quant_step ? float(1.0 / quant_step) : 0.f;

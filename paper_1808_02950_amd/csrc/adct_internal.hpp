@@ -321,6 +321,24 @@ enum Mode { kEncode = 0, kDecode = 1, kEvaluate = 2, kProbe = 3 };
 // Constants of an integer matrix given at run time (ADCT_CUSTOM, and the
 // float-coefficient decode of the built-in matrices), a second kernel argument
 // of the run-time codec kernels.  All entries are wave-uniform.
+// Exact rounding of dequantised reconstructions that can sit on a half (a step
+// for which step / mu has an even reduced denominator for some class with
+// n_k n_l = mu^2).  Write n_k n_l = mu^2 r with r squarefree: 1 / sqrt(n_k n_l)
+// = w sqrt(r) / D with D = lcm(mu r) and w = D / (mu r), so a pixel is
+//   (step / D) (N_0 + N_1 sqrt(p) + N_2 sqrt(q) + N_3 sqrt(r3)),
+// N_c the sum over the coefficients of class c of C_kl T[k][x] T[l][y] w_kl,
+// where the generators p, q give every r that occurs (r3 the squarefree part
+// of p q, sqrt(p q) = g sqrt(r3)).  The kernel decides a pixel within tol of a
+// half by the exact sign of the difference in that field.
+struct RtSettle {
+    int32_t on;          // nonzero: decide pixels near a half exactly
+    int32_t p, q, g;     // generators (1 when absent), sqrt(p q) = g sqrt(r3)
+    int64_t D;
+    double tol_c;        // tolerance per unit of sum |C_kl| s_k s_l (float64 error bound)
+    int32_t w[64];       // w_kl
+    int8_t cls[64];      // 0: rational, 1: sqrt p, 2: sqrt q, 3: sqrt r3
+};
+
 struct RtMatArgs {
     int32_t t[64];       // T[k][m] at 8k + m
     int32_t mu[64];      // mu with mu^2 = n_k n_l, 0 when n_k n_l is not a square
@@ -329,7 +347,14 @@ struct RtMatArgs {
     double skl[64];      // s_k s_l = 1 / sqrt(n_k n_l)
     int64_t L;           // L1^2, the exact inverse's denominator
     double inv_2L;       // 1 / (2 L)
+    RtSettle st;
 };
+
+// Bounds of the exact near-half decision (checked on the host): every field
+// component below 2^52 in magnitude, p q <= 1024, so the second-level values
+// stay inside 128-bit words and their squares inside 256 bits.
+constexpr int64_t kSettleMaxComp = int64_t(1) << 52;
+constexpr int32_t kSettleMaxPQ = 1024;
 
 // Word sizes the run-time kernels assume (checked on the host before launch).
 constexpr int64_t kRtMaxL = int64_t(1) << 53;       // L, so 511 L < 2^63

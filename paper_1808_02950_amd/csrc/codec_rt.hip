@@ -11,6 +11,7 @@
 // table (quantiser classes, scales, inverse weights) comes from the kernel
 // argument the host fills.
 #include "codec_tile.hpp"
+#include "settle.hpp"
 
 namespace adct {
 namespace {
@@ -33,6 +34,32 @@ __device__ __forceinline__ int rne_div_clip_rt(int64_t n, int64_t L, double inv_
         rem -= l2;
     }
     return q - int((rem == 0) & (q & 1));
+}
+
+// ---- exact near-half decisions (quantiser steps that admit exact halves)
+
+// Pixel (x, y) of a dequantised block, rounded half to even exactly, given its
+// float64 value v near the half fl + 1/2 (fl = floor(v)): the sign of
+// D (2 pixel - 2 fl - 1) = 2 step sum_c N_c sqrt(r_c) - (2 fl + 1) D decides.
+template <int BAND>
+__device__ int settle_pixel(const RtMatArgs &m, const int (&C)[8][8], int step, int x, int y, double v) {
+    constexpr int KB = BAND + 1 < 8 ? BAND + 1 : 8;
+    int64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+    for (int k = 0; k < KB; ++k)
+        for (int l = 0; l < KB; ++l) {
+            if (k + l > BAND) continue;
+            const int64_t t = int64_t(C[k][l]) * (m.t[8 * k + x] * m.t[8 * l + y]) * m.st.w[8 * k + l];
+            const int c = m.st.cls[8 * k + l];
+            n0 += c == 0 ? t : 0;
+            n1 += c == 1 ? t : 0;
+            n2 += c == 2 ? t : 0;
+            n3 += c == 3 ? t : 0;
+        }
+    const int64_t fl = int64_t(floor(v));
+    const i128 g = m.st.g, s2 = 2 * i128(step);
+    const i128 a = g * (s2 * n0 - i128(2 * fl + 1) * m.st.D);
+    const int s = sgn_field(a, g * s2 * n1, g * s2 * n2, s2 * n3, uint32_t(m.st.p), uint32_t(m.st.q));
+    return int(s > 0 ? fl + 1 : s < 0 ? fl : fl + (fl & 1));
 }
 
 // FIN: the decoder reads float32 B (coef_f) instead of integer coefficients.
@@ -158,6 +185,18 @@ __device__ __forceinline__ void process_tile_rt(const CodecArgs &a, const RtMatA
     } else {
         // float64: A = C_hat^T B' C_hat with B' = step q (quantised) or the B read,
         // C_hat = S T, so B'_kl s_k s_l enters the integer matrix products
+        // near-half tolerance of the block: the float64 error bound
+        // tol_c sum |C_kl| s_k s_l, at least 1e-6
+        double tol = 1e-6;
+        if (QUANT && !FIN && m.st.on) {
+            double sc = 0.0;
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+#pragma unroll
+                for (int l = 0; l < KB; ++l)
+                    if (k + l <= BAND) sc += fabs(double(C[k][l])) * m.skl[8 * k + l];
+            tol = fmax(tol, sc * m.st.tol_c);
+        }
         double W[KB][KB];
 #pragma unroll
         for (int k = 0; k < KB; ++k)
@@ -190,6 +229,11 @@ __device__ __forceinline__ void process_tile_rt(const CodecArgs &a, const RtMatA
 #pragma unroll
                 for (int l = 0; l < KB; ++l) acc = fma(double(m.t[8 * l + y]), U[l], acc);
                 q[y] = clamp255(rne_i32(acc));
+                if (QUANT && !FIN && m.st.on) {
+                    const double h = floor(acc) + 0.5;
+                    if (fabs(acc - h) < tol && acc > -1.0 && acc < 256.0)
+                        q[y] = clamp255(settle_pixel<BAND>(m, C, a.step, x, y, acc));
+                }
             }
             const u32x2 v = emit_row(q, MODE == kEvaluate ? pix[x][0] : 0u,
                                      MODE == kEvaluate ? pix[x][1] : 0u, sq, cross);

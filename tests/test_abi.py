@@ -89,9 +89,6 @@ FAKE = ctypes.c_void_p(4096)          # never dereferenced: every case fails val
     ((FAKE, 8, 8, 8, A.T1, None, 10, -1, FAKE, None, None), -3),        # step < 0
     ((FAKE, 8, 8, 8, A.LO, None, 10, 0, FAKE, None, None), -4),         # LO into int16
     ((FAKE, 8, 8, 8, 42, None, 10, 0, FAKE, None, None), -1),           # unknown id
-    ((FAKE, 8, 8, 8, A.T1, None, 10, 5, FAKE, None, None), -7),         # step with exact ties
-    ((FAKE, 8, 8, 8, A.T1, None, 10, 12, FAKE, None, None), -7),
-    ((FAKE, 8, 8, 8, A.LO, None, 10, 16, FAKE, None, None), -7),
 ])
 def test_encode_argument_errors(args, expect):
     assert _call("adct_encode_blocks", *args) == expect
@@ -127,26 +124,51 @@ def test_plane_height_bound():
     assert A.lib().adct_evaluate_stream(FAKE, 0, 1, big, 1, A.T1, None, 10, 0, None, None, 0, sse, None) == -2
 
 
-def test_tie_free_quantiser_steps_accepted():
+def test_quantiser_steps_accepted():
+    """Tie-free steps and steps that admit exact halves (decided exactly in the
+    field of the row norms' square roots) are both accepted for every built-in
+    matrix, at the zonal bands of r = 10 and r = 64, up to the largest step."""
     lib = A.lib()
-    for tid, step in [(A.T1, 8), (A.T1, 16), (A.T1, 24), (A.T4, 8), (A.T6, 40), (A.LO, 32)]:
-        assert lib.adct_check_codec_args(tid, None, 10, step, 1) == 0
-    for tid, step in [(A.T1, 4), (A.T2, 20), (A.LO, 16), (A.RDCT, 6)]:
-        assert lib.adct_check_codec_args(tid, None, 10, step, 1) == -7
+    for tid, step in [(A.T1, 8), (A.T1, 16), (A.T1, 24), (A.T4, 8), (A.T6, 40), (A.LO, 32),
+                      (A.T1, 4), (A.T1, 5), (A.T2, 20), (A.LO, 16), (A.RDCT, 6), (A.T6, 3), (A.T4, 1)]:
+        for r in (10, 64):
+            assert lib.adct_check_codec_args(tid, None, r, step, 1) == 0, (tid, step, r)
+    for tid in (A.T1, A.T2, A.LO, A.T6, A.RDCT, A.T4):
+        assert lib.adct_check_codec_args(tid, None, 64, 65535, 1) == 0
+        assert lib.adct_check_codec_args(tid, None, 64, 65533, 1) == 0
     assert lib.adct_check_codec_args(A.LO, None, 10, 0, 1) == -4
     assert lib.adct_check_codec_args(A.LO, None, 10, 0, 0) == 0
+
+
+def test_three_independent_roots_refused():
+    """Row norms (2, 2, 3, 2, 6, 5, 5, 1) bring in sqrt 2, sqrt 3 and sqrt 5:
+    with a step that admits exact halves the full band (r = 64) cannot be
+    decided with two generators (ADCT_ENOTSUP); the band of r = 10 only meets
+    sqrt 6, and tie-free steps need no decision."""
+    t = np.zeros((8, 8), dtype=np.int64)
+    t[0:2, 0:2] = [[1, 1], [1, -1]]
+    t[2:5, 2:5] = [[1, 1, 1], [1, -1, 0], [1, 1, -2]]
+    t[5:7, 5:7] = [[1, 2], [2, -1]]
+    t[7, 7] = 1
+    m = A._matrix_struct(t)
+    n = [int(v) for v in np.diag(t @ t.T)]
+    assert n == [2, 2, 3, 2, 6, 5, 5, 1], n
+    lib = A.lib()
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 64, 1, 0) == -7
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 1, 0) == 0
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 64, 0, 0) == 0
 
 
 def test_custom_matrix_validation_host_only():
     """ADCT_CUSTOM takes any int8 matrix with orthogonal rows: the caller's n must
     be diag(T T^T); a missing matrix, non-orthogonal rows or a wrong n are
-    ADCT_EINVAL; the quantiser-step rule and the int16 bound apply as for the
+    ADCT_EINVAL; the quantiser steps and the int16 bound work as for the
     built-in matrices."""
     lib = A.lib()
     m = A._matrix_struct(M.T1)
     assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 0, 1) == 0
     assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 16, 1) == 0
-    assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 12, 1) == -7
+    assert lib.adct_check_codec_args(A.CUSTOM, m, 10, 12, 1) == 0       # ties decided exactly
     assert lib.adct_check_codec_args(A.CUSTOM, None, 10, 0, 1) == -1
     bad_n = A._matrix_struct(M.T1)
     bad_n.n[2] += 1
