@@ -823,18 +823,28 @@ def patch_pairs(images, table, transform="T1", quant_step: int = 0, size: int = 
     return out, orig
 
 
+def shuffled_pairs(recon, orig, seed: int = 0, device="cuda"):
+    """The (recon, orig) host pairs in train_filter's seeded order, on the device."""
+    import torch
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(len(recon))
+    return (torch.from_numpy(np.ascontiguousarray(recon[perm])).to(device),
+            torch.from_numpy(np.ascontiguousarray(orig[perm])).to(device))
+
+
 def train_filter(params, recon, orig, steps: int, batch: int = 64, lr: float = 1e-3, lr_final: float = 1e-4,
                  seed: int = 0, device="cuda", log_every: int = 0):
     """Adam training of the post-filter on the GPU.  recon, orig: host uint8
-    (n, H, W) pairs (see patch_pairs).  The pairs are shuffled once (seeded)
-    and uploaded; step s trains on the next contiguous batch (wrapping), with
-    the learning rate decayed geometrically from lr to lr_final.  Returns
-    (trained params as a CUDA float32 tensor, per-step losses as numpy)."""
+    (n, H, W) pairs (see patch_pairs), shuffled once (seeded) and uploaded, or
+    CUDA uint8 tensors used as they are (see shuffled_pairs); step s trains on
+    the next contiguous batch (wrapping), with the learning rate decayed
+    geometrically from lr to lr_final.  Returns (trained params as a CUDA
+    float32 tensor, per-step losses as numpy)."""
     import torch
     n, h, w = recon.shape
-    perm = np.random.Generator(np.random.PCG64(seed)).permutation(n)
-    rd = torch.from_numpy(np.ascontiguousarray(recon[perm])).to(device)
-    od = torch.from_numpy(np.ascontiguousarray(orig[perm])).to(device)
+    if isinstance(recon, torch.Tensor):
+        rd, od = recon, orig
+    else:
+        rd, od = shuffled_pairs(recon, orig, seed, device)
     tr = FilterTrainer(params, batch, h, w, lr=lr, device=device)
     losses = torch.empty(steps, dtype=torch.float32, device=device)
     decay = (lr_final / lr) ** (1.0 / max(1, steps - 1))
