@@ -104,6 +104,20 @@ int adct_version(void);
  * wave); k > 0 = at most k.  Results do not depend on it. */
 adct_status adct_codec_set_schedule(int workgroups_per_cu);
 
+/* Device memory the library keeps between calls on the current device, and
+ * how to give it back.  The searches (adct_derive_transform and the other
+ * search entry points) keep grow-only buffers per device: the enumerated space
+ * (8 bytes a vector, 9^8 = 43 M vectors: 344 MB), its flags and bin bytes, the
+ * query buffers and the feasible-list arenas (the largest closure searches
+ * reach several GB; a search refuses to grow them past 32 GB).
+ * adct_coding_gain_sweep keeps one staging buffer (8 (65 n_t + n_rho) bytes
+ * at its largest call).  Both are reused by later calls and otherwise kept
+ * until the process ends.  This call frees them for the current device (it
+ * waits for a search or sweep running on it) and reports the bytes freed
+ * (nullable); the next call allocates again.  Batch plans, filter workspaces
+ * and the no-allocation sweep's fixed array are not affected. */
+adct_status adct_release_caches(int64_t *bytes_released);
+
 /* Fill *out with a built-in matrix (not ADCT_DCT / ADCT_CUSTOM).  Host only. */
 adct_status adct_matrix_get(adct_transform_id id, adct_matrix *out);
 
@@ -299,8 +313,9 @@ adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t frame_stride, i
  * of Sec. 4.3 is its difference to the exact DCT's): 10 sum_i -log10(A_i B_i)/8,
  * A_i = sum_jk c_ij c_ik rho^|j-k|, B_i the squared norm of row i of C_hat^-1.
  * c_hat: host double [n_t][64] row-major; rho: host double [n_rho] in [0, 1);
- * cg_out: host double [n_t][n_rho] (dB).  Synchronises `stream`; allocates and
- * frees its own device buffers.  Errors: ADCT_EINVAL null; ADCT_ERANGE counts
+ * cg_out: host double [n_t][n_rho] (dB).  Synchronises `stream`; stages in a
+ * grow-only device buffer kept between calls (adct_release_caches frees it);
+ * calls on one device are serialised.  Errors: ADCT_EINVAL null; ADCT_ERANGE counts
  * below 1, n_t * n_rho > 2^26, rho outside [0, 1). */
 adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, const double *rho, int n_rho,
                                    double *cg_out, adct_stream_t stream);

@@ -54,6 +54,7 @@ _SIGNATURES = {
     "adct_version": (_I, []),
     "adct_matrix_get": (_I, [_I, ctypes.POINTER(Matrix)]),
     "adct_codec_set_schedule": (_I, [_I]),
+    "adct_release_caches": (_I, [ctypes.POINTER(_I64)]),
     "adct_check_codec_args": (_I, [_I, ctypes.POINTER(Matrix), _I, _I, _I]),
     "adct_transform_bounds": (_I, [_I, ctypes.POINTER(Matrix), _I, _I,
                                    ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -215,6 +216,14 @@ def codec_set_schedule(workgroups_per_cu: int) -> None:
     -1 = one tile per wave, k > 0 = at most k workgroups per CU."""
     _check(lib().adct_codec_set_schedule(int(workgroups_per_cu)))
 
+
+
+def release_caches() -> int:
+    """adct_release_caches: free the device buffers the searches and the
+    coding-gain sweep keep on the current device; returns the bytes freed."""
+    n = _I64()
+    _check(lib().adct_release_caches(ctypes.byref(n)))
+    return int(n.value)
 
 def matrix_get(t) -> np.ndarray:
     m = Matrix()

@@ -636,6 +636,14 @@ adct_status adct_codec_set_schedule(int workgroups_per_cu) {
     return ADCT_OK;
 }
 
+adct_status adct_release_caches(int64_t *bytes_released) {
+    int dev = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    const int64_t n = release_search_cache(dev) + release_gain_cache(dev);
+    if (bytes_released) *bytes_released = n;
+    return ADCT_OK;
+}
+
 adct_status adct_matrix_get(adct_transform_id id, adct_matrix *out) {
     if (!out) return fail(ADCT_EINVAL, "out is null");
     if (!is_builtin_int(id)) return fail(ADCT_EINVAL, "not a built-in integer transform");

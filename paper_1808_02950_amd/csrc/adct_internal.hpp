@@ -366,6 +366,11 @@ adct_status launch_codec_rt(int band, bool quant, bool float_in, Mode mode, cons
 
 adct_status launch_dct(Mode mode, const DctArgs &a, int total_waves, hipStream_t s);
 
+// Free the grow-only device buffers of the searches and of the coding-gain
+// sweep on device `dev`; each returns the bytes it released.
+int64_t release_search_cache(int dev);
+int64_t release_gain_cache(int dev);
+
 // Codec launch schedule: resident 4-wave workgroups per CU (0 = as many as
 // occupancy allows, -1 = one tile per wave, no persistence).
 int codec_wgs_per_cu();

@@ -674,12 +674,13 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
 }
 
 // fixed-order sums over workgroups: deterministic gradient and loss.  Blocks
-// below kRedParamBlocks take 16 consecutive weight-gradient entries; their 16
-// row groups each sum every 16th partial row (all loads of a thread in flight
-// together) and the group sums are added in a fixed order.  The last two
+// below kRedParamBlocks take 64 consecutive weight-gradient entries (256
+// contiguous bytes of every partial row); their 4 row groups each sum every
+// 4th partial row (16 loads of a thread in flight together) and the group sums
+// are added in a fixed order.  The last two
 // blocks sum the per-wave partials of the loss-gradient kernel (b3's gradient,
 // then the loss) with all 256 threads and a fixed-order tree.
-constexpr int kRedCols = 16, kRedGroups = 16;
+constexpr int kRedCols = 64, kRedGroups = 4;
 constexpr int kRedParamBlocks = (kOffB3 + kRedCols - 1) / kRedCols;
 
 // Adam's state and hyper-parameters (c1, c2: the bias corrections of the step)

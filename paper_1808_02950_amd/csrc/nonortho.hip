@@ -342,6 +342,26 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     return ADCT_OK;
 }
 
+// One grow-only staging buffer per device for adct_coding_gain_sweep (the
+// call synchronises its stream before it returns, so the next call on the
+// device may reuse it); the lock serialises calls on one device.
+struct GainCache {
+    std::mutex lock;
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+GainCache g_gain[64];
+
+int64_t adct::release_gain_cache(int dev) {
+    if (dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> hold(g_gain[dev].lock);
+    const int64_t n = int64_t(g_gain[dev].bytes);
+    if (g_gain[dev].p) (void)hipFree(g_gain[dev].p);
+    g_gain[dev].p = nullptr;
+    g_gain[dev].bytes = 0;
+    return n;
+}
+
 extern "C" adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, const double *rho, int n_rho,
                                               double *cg_out, adct_stream_t stream) {
     if (!c_hat || !rho || !cg_out) return fail(ADCT_EINVAL, "c_hat, rho and cg_out are required");
@@ -351,12 +371,22 @@ extern "C" adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, cons
         if (!(rho[j] >= 0.0 && rho[j] < 1.0)) return fail(ADCT_ERANGE, "rho must be in [0, 1)");
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     const size_t nc = size_t(n_t) * 64, no = size_t(n_t) * n_rho;
-    double *dc = nullptr, *dr = nullptr, *dout = nullptr;
+    int dev = 0;
+    ADCT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(ADCT_EDEVICE, "device index beyond the library's table");
+    GainCache &gc = g_gain[dev];
+    std::lock_guard<std::mutex> hold(gc.lock);
+    const size_t need = (nc + size_t(n_rho) + no) * sizeof(double);
+    if (gc.bytes < need) {
+        if (gc.p) (void)hipFree(gc.p);
+        gc.p = nullptr;
+        gc.bytes = 0;
+        ADCT_HIP(hipMalloc(&gc.p, need));
+        gc.bytes = need;
+    }
+    double *dc = static_cast<double *>(gc.p), *dr = dc + nc, *dout = dr + n_rho;
     adct_status st = ADCT_OK;
-    hipError_t e = hipMalloc(&dc, nc * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&dr, size_t(n_rho) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&dout, no * sizeof(double));
-    if (e == hipSuccess) e = hipMemcpyAsync(dc, c_hat, nc * sizeof(double), hipMemcpyHostToDevice, hs);
+    hipError_t e = hipMemcpyAsync(dc, c_hat, nc * sizeof(double), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(dr, rho, size_t(n_rho) * sizeof(double), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_coding_gain, dim3(unsigned((no + 255) / 256)), dim3(256), 0, hs, dc, n_t, dr, n_rho,
@@ -366,9 +396,6 @@ extern "C" adct_status adct_coding_gain_sweep(const double *c_hat, int n_t, cons
     if (e == hipSuccess) e = hipMemcpyAsync(cg_out, dout, no * sizeof(double), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) st = hip_fail(e, "coding gain sweep");
-    if (dc) (void)hipFree(dc);
-    if (dr) (void)hipFree(dr);
-    if (dout) (void)hipFree(dout);
     return st;
 }
 

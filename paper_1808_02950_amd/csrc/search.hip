@@ -417,6 +417,25 @@ struct SearchCache {
 constexpr int kCacheDevices = 64;
 SearchCache g_cache[kCacheDevices];
 
+}  // namespace
+
+// free the current device's search buffers (waits for a running search on it)
+int64_t release_search_cache(int dev) {
+    if (dev < 0 || dev >= kCacheDevices) return 0;
+    SearchCache &c = g_cache[dev];
+    std::lock_guard<std::mutex> hold(c.lock);
+    int64_t n = 0;
+    for (int i = 0; i < kCacheSlots; ++i) {
+        if (c.slot[i]) (void)hipFree(c.slot[i]);
+        n += int64_t(c.bytes[i]);
+        c.slot[i] = nullptr;
+        c.bytes[i] = 0;
+    }
+    return n;
+}
+
+namespace {
+
 struct Space {
     int b = 0;
     int8_t digits[9] = {};
@@ -906,9 +925,14 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
     ADCT_HIP(hipMemcpyAsync(hist.data(), dhist.p, sizeof(unsigned) * hist.size(), hipMemcpyDeviceToHost, s));
     ADCT_HIP(hipStreamSynchronize(s));
     // per row the highest bin whose cumulative count (from the smallest angle)
-    // reaches k + a margin, so the tie group at position k lies inside
+    // reaches k + a margin.  Exact ties share a bin, so they are collected
+    // whole; a chain of near-ties (each within kTieEps) could still cross the
+    // threshold bin, so after ranking the tie group at position k must end
+    // before the last collected candidate.  Rows where it does not lower
+    // their threshold by one bin and the rows are collected again.
     Thresholds th;
-    int64_t total = 0;
+    int bins[8];
+    int64_t cums[8];
     for (int r = 0; r < 8; ++r) {
         int64_t cum = 0;
         int bn = kHistBins - 1;
@@ -917,53 +941,70 @@ adct_status adct_search_topk(const int8_t *P, int nP, int k, int primitive, int8
             if (cum >= int64_t(k) + 64) break;
         }
         if (bn < 0) bn = 0;
-        th.bin[r] = bn;
-        th.cap[r] = cum;
-        th.off[r] = total;
-        total += cum;
+        bins[r] = bn;
+        cums[r] = cum;
     }
-    DevBuf didx, dcos, dcnt;
-    if ((st = dalloc<int64_t>(didx, total))) return st;
-    if ((st = dalloc<double>(dcos, total))) return st;
-    if ((st = dalloc<unsigned long long>(dcnt, 8))) return st;
-    ADCT_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(unsigned long long) * 8, s));
-    bool bytes_ok = true;
-    for (int r = 0; r < 8; ++r) bytes_ok &= th.bin[r] <= 254;
-    if (bytes_ok)
-        hipLaunchKernelGGL(k_topk_collect_codes, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)codes,
-                           (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(), th, (int64_t *)didx.p,
-                           (double *)dcos.p, (unsigned long long *)dcnt.p);
-    else
-        hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec,
-                           (const uint8_t *)sp.prim, primitive, (const double *)sp.inv.p, dct_rows(), th,
-                           (int64_t *)didx.p, (double *)dcos.p, (unsigned long long *)dcnt.p);
-    ADCT_HIP(hipGetLastError());
-    std::vector<int64_t> idx(std::max<int64_t>(total, 1));
-    std::vector<double> cs(std::max<int64_t>(total, 1));
-    std::vector<unsigned long long> cnt(8);
-    ADCT_HIP(hipMemcpyAsync(idx.data(), didx.p, sizeof(int64_t) * total, hipMemcpyDeviceToHost, s));
-    ADCT_HIP(hipMemcpyAsync(cs.data(), dcos.p, sizeof(double) * total, hipMemcpyDeviceToHost, s));
-    ADCT_HIP(hipMemcpyAsync(cnt.data(), dcnt.p, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, s));
-    ADCT_HIP(hipStreamSynchronize(s));
-    for (int r = 0; r < 8; ++r) {
-        if (int64_t(cnt[r]) != th.cap[r]) return fail(ADCT_EDEVICE, "top-k collection count mismatch");
-        std::vector<Cand> c(size_t(th.cap[r]));
-        for (int64_t j = 0; j < th.cap[r]; ++j) {
-            c[j].idx = idx[th.off[r] + j] + 1;
-            c[j].cos = cs[th.off[r] + j];
-            int8_t v[8];
-            decode_index(sp, c[j].idx, v);
-            c[j].norm2 = norm2_of(v);
+    for (;;) {
+        int64_t total = 0;
+        for (int r = 0; r < 8; ++r) {
+            th.bin[r] = bins[r];
+            th.cap[r] = cums[r];
+            th.off[r] = total;
+            total += cums[r];
         }
-        canonical_sort(c);
-        if (int64_t(c.size()) < k) return fail(ADCT_ERANGE, "fewer candidates than k");
-        for (int j = 0; j < k; ++j) {
-            decode_index(sp, c[j].idx, vec_out + (int64_t(r) * k + j) * 8);
-            idx_out[int64_t(r) * k + j] = c[j].idx;
-            cos_out[int64_t(r) * k + j] = c[j].cos;
+        DevBuf didx, dcos, dcnt;
+        if ((st = dalloc<int64_t>(didx, total))) return st;
+        if ((st = dalloc<double>(dcos, total))) return st;
+        if ((st = dalloc<unsigned long long>(dcnt, 8))) return st;
+        ADCT_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(unsigned long long) * 8, s));
+        bool bytes_ok = true;
+        for (int r = 0; r < 8; ++r) bytes_ok &= th.bin[r] <= 254;
+        if (bytes_ok)
+            hipLaunchKernelGGL(k_topk_collect_codes, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)codes,
+                               (const uint2 *)sp.vec, (const double *)sp.inv.p, dct_rows(), th,
+                               (int64_t *)didx.p, (double *)dcos.p, (unsigned long long *)dcnt.p);
+        else
+            hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(256), 0, s, sp.n, (const uint2 *)sp.vec,
+                               (const uint8_t *)sp.prim, primitive, (const double *)sp.inv.p, dct_rows(), th,
+                               (int64_t *)didx.p, (double *)dcos.p, (unsigned long long *)dcnt.p);
+        ADCT_HIP(hipGetLastError());
+        std::vector<int64_t> idx(std::max<int64_t>(total, 1));
+        std::vector<double> cs(std::max<int64_t>(total, 1));
+        std::vector<unsigned long long> cnt(8);
+        ADCT_HIP(hipMemcpyAsync(idx.data(), didx.p, sizeof(int64_t) * total, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(cs.data(), dcos.p, sizeof(double) * total, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipMemcpyAsync(cnt.data(), dcnt.p, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, s));
+        ADCT_HIP(hipStreamSynchronize(s));
+        bool again = false;
+        for (int r = 0; r < 8; ++r) {
+            if (int64_t(cnt[r]) != th.cap[r]) return fail(ADCT_EDEVICE, "top-k collection count mismatch");
+            std::vector<Cand> c(size_t(th.cap[r]));
+            for (int64_t j = 0; j < th.cap[r]; ++j) {
+                c[j].idx = idx[th.off[r] + j] + 1;
+                c[j].cos = cs[th.off[r] + j];
+                int8_t v[8];
+                decode_index(sp, c[j].idx, v);
+                c[j].norm2 = norm2_of(v);
+            }
+            canonical_sort(c);
+            if (int64_t(c.size()) < k) return fail(ADCT_ERANGE, "fewer candidates than k");
+            size_t e = size_t(k) - 1;
+            while (e + 1 < c.size() && c[e].cos - c[e + 1].cos <= kTieEps) ++e;
+            if (e + 1 == c.size() && bins[r] > 0) {
+                // the group may go on below the threshold: take one more bin
+                --bins[r];
+                cums[r] += hist[r * kHistBins + bins[r]];
+                again = true;
+                continue;
+            }
+            for (int j = 0; j < k; ++j) {
+                decode_index(sp, c[j].idx, vec_out + (int64_t(r) * k + j) * 8);
+                idx_out[int64_t(r) * k + j] = c[j].idx;
+                cos_out[int64_t(r) * k + j] = c[j].cos;
+            }
         }
+        if (!again) return ADCT_OK;
     }
-    return ADCT_OK;
 }
 
 adct_status adct_orthogonal_tuples(const int8_t *lists, const int *len, int32_t *out, int64_t cap,

@@ -166,3 +166,16 @@ def test_topk_extended_set_primitive(cuda):
         assert np.array_equal(idx[r], ref[r]["idx"])
         assert np.array_equal(vec[r], ref[r]["vec"])
         np.testing.assert_allclose(cos[r], ref[r]["cos"], rtol=0, atol=1e-15)
+
+
+def test_release_caches_then_search_again(cuda):
+    """adct_release_caches frees the search buffers kept on the device (and the
+    coding-gain sweep's); the next search allocates again and gives the same
+    ranking; a second release finds nothing left."""
+    vec, idx, cos = A.search_topk(S.P2, 20)
+    A.coding_gain_sweep([M.T1.astype(np.float64) / np.sqrt((M.T1 ** 2).sum(1, keepdims=True))], [0.9])
+    freed = A.release_caches()
+    assert freed > 0
+    assert A.release_caches() == 0
+    vec2, idx2, cos2 = A.search_topk(S.P2, 20)
+    assert np.array_equal(idx, idx2) and np.array_equal(vec, vec2) and np.array_equal(cos, cos2)
