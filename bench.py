@@ -609,6 +609,9 @@ def main():
                     help="patches of 64x64 per training step")
     ap.add_argument("--codec-only", action="store_true",
                     help="time only the headline codec step and its bandwidth probe (profiling runs)")
+    ap.add_argument("--dct-only", action="store_true",
+                    help="time only the headline codec step, its probe and the exact-DCT comparator "
+                         "(profiling runs)")
     ap.add_argument("--schedule", type=int, default=0,
                     help="resident workgroups per CU of the codec grid (0 = occupancy limit, "
                          "-1 = one tile per wave)")
@@ -620,7 +623,8 @@ def main():
         sys.exit(2)
 
     # training images are drawn before the GPU is touched
-    fdata = filter_images(args.filter_patches, 4096) if args.filter_patches and not args.codec_only else None
+    fdata = (filter_images(args.filter_patches, 4096)
+             if args.filter_patches and not (args.codec_only or args.dct_only) else None)
 
     import numpy as np
     import torch
@@ -723,6 +727,10 @@ def main():
     ev3.record()
     torch.cuda.synchronize()
     dct_ms = ev2.elapsed_time(ev3) / dct_steps
+    if args.dct_only:
+        print(json.dumps({"metric": "dct-only profiling run", "kernel_ms": round(kernel_ms, 4),
+                          "dct_ms": round(dct_ms, 4)}), flush=True)
+        return
     dct_frame, dct_planes = psnrs(sse_dct)
     # algorithmic bytes: every pixel read once, every reconstructed pixel written once
     dct_bytes = 2 * samples
