@@ -172,6 +172,9 @@ struct ConvArgs {
     float *y_out;              //                y (nullable)
     float *part;               //                per wave (sum d^2, sum g3)
     float gscale;              //                2 / pixel count
+    const uint16_t *w1;        // fused layers 1 + 2: layer 1's packed A operands,
+    const float *bias1;        //   its bias,
+    uint16_t *dst1;            //   and where its activation a1 is written
     int H, W, strips, chunks, total;
 };
 
@@ -312,6 +315,94 @@ __global__ __launch_bounds__(256) void k_conv32(const ConvArgs a) {
         conv32_step<EPI, 0>(a, F, bv, acc, B, s, T, plane, n, g);
         conv32_step<EPI, 1>(a, F, bv, acc, B, s + 1, T, plane, n, g);
         conv32_step<EPI, 2>(a, F, bv, acc, B, s + 2, T, plane, n, g);
+    }
+}
+
+// Layers 1 and 2 in one pass.  Layer 2 reads layer 1's activation at three
+// column shifts; here each input row of it is computed in the wave instead of
+// loaded: for shift dx the lane's B operand holds the 3 x 3 taps of x around
+// pixel (row, c0 + n + dx - 1) (lanes g < 3, tap row g), one mma16 per half of
+// the 32 channels gives a1 there in exactly the slot layout layer 2 reads as
+// its B operand, and positions outside the image are zero (layer 2's padding).
+// The same products on the same operands as k_conv1, so a1 and a2 are the
+// values the two kernels give; the centre shift of the tile's own rows is
+// written as a1 for the backward pass.  x taps of the next input row are
+// loaded one step ahead.
+struct XTaps {
+    uint16_t v[5];     // bf16 of x - 128 (0 outside the image) at columns c0 + n - 2 .. c0 + n + 2
+};
+
+__device__ __forceinline__ void gather_taps(const ConvArgs &a, int64_t plane, int rho, int c0, int n, int g,
+                                            XTaps &t) {
+    const int sy = rho + g - 1;
+    const bool rok = g < 3 && sy >= 0 && sy < a.H;
+    const uint8_t *src = static_cast<const uint8_t *>(a.src) + plane + int64_t(rok ? sy : 0) * a.W;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int sx = c0 + n + j - 2;
+        t.v[j] = (rok && sx >= 0 && sx < a.W) ? bf16_bits(float(int(src[sx]) - 128)) : uint16_t(0);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void conv12_step(const ConvArgs &a, const uint4 (&F)[9][2], const uint2 (&A1)[2],
+                                            const f32x4 (&b1)[2], const f32x4 (&bv)[2], f32x4 (&acc)[3][2],
+                                            XTaps &X, int s, const WaveTile &T, int64_t plane, int n, int g) {
+    const XTaps Xc = X;
+    const int rho = T.y0 - 1 + s;
+    if (s + 1 < kConvRows + 2) gather_taps(a, plane, rho + 1, T.c0, n, g, X);
+    uint4 Bc[3];
+    const bool rok = rho >= 0 && rho < a.H;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        const uint2 B = {uint32_t(Xc.v[dx]) | (uint32_t(Xc.v[dx + 1]) << 16), uint32_t(Xc.v[dx + 2])};
+        const uint4 v = pack_relu(mma16(A1[0], B, b1[0]), mma16(A1[1], B, b1[1]));
+        const int col = T.c0 + n + dx - 1;
+        Bc[dx] = (rok && col >= 0 && col < a.W) ? v : uint4{0u, 0u, 0u, 0u};
+    }
+    if (s >= 1 && s <= kConvRows)
+        *reinterpret_cast<uint4 *>(a.dst1 + (plane + int64_t(rho) * a.W + T.c0 + n) * 32 + 8 * g) = Bc[1];
+    const int64_t pix = plane + int64_t(T.y0 + s - 2) * a.W + T.c0 + n;
+    constexpr int S0 = P, S1 = (P + 2) % 3, S2 = (P + 1) % 3;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        acc[S0][h] = mma32(F[0][h], Bc[0], bv[h]);
+        acc[S0][h] = mma32(F[1][h], Bc[1], acc[S0][h]);
+        acc[S0][h] = mma32(F[2][h], Bc[2], acc[S0][h]);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) acc[S1][h] = mma32(F[3 + dx][h], Bc[dx], acc[S1][h]);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) acc[S2][h] = mma32(F[6 + dx][h], Bc[dx], acc[S2][h]);
+    }
+    if (s >= 2) store32<kRelu>(a, pix, g, acc[S2][0], acc[S2][1], uint4{0u, 0u, 0u, 0u});
+}
+
+// Held to 3 waves per SIMD (164 VGPRs): uncapped it takes 176 and runs two,
+// slower than the two separate kernels it replaces.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_conv12(const ConvArgs a) {
+    __shared__ uint4 sw[9 * 2 * 64];
+    for (int i = threadIdx.x; i < 9 * 2 * 64; i += 256) sw[i] = reinterpret_cast<const uint4 *>(a.w)[i];
+    __syncthreads();
+    WaveTile T;
+    int gw;
+    if (!wave_tile(a, T, gw)) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    uint4 F[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) F[t][h] = sw[(t * 2 + h) * 64 + lane];
+    const uint2 A1[2] = {reinterpret_cast<const uint2 *>(a.w1)[lane], reinterpret_cast<const uint2 *>(a.w1)[64 + lane]};
+    const f32x4 b1[2] = {bias4(a.bias1, 4 * g), bias4(a.bias1, 16 + 4 * g)};
+    const f32x4 bv[2] = {bias4(a.bias, 4 * g), bias4(a.bias, 16 + 4 * g)};
+    f32x4 acc[3][2] = {};
+    const int64_t plane = int64_t(T.img) * a.H * a.W;
+    XTaps X;
+    gather_taps(a, plane, T.y0 - 1, T.c0, n, g, X);
+    for (int s = 0; s < kConvRows + 2; s += 3) {
+        conv12_step<0>(a, F, A1, b1, bv, acc, X, s, T, plane, n, g);
+        conv12_step<1>(a, F, A1, b1, bv, acc, X, s + 1, T, plane, n, g);
+        conv12_step<2>(a, F, A1, b1, bv, acc, X, s + 2, T, plane, n, g);
     }
 }
 
@@ -1137,12 +1228,10 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     c.chunks = H / kConvRows;
     c.total = n * c.strips * c.chunks;
     const dim3 grid((c.total + 3) / 4), blk(256);
-    ConvArgs c1 = c;   // layer 1
-    c1.src = recon; c1.w = packed + kPF1; c1.bias = bias; c1.dst = a1;
-    hipLaunchKernelGGL((k_conv1<true, kRelu>), grid, blk, 0, s, c1);
-    ConvArgs c2 = c;   // layer 2
-    c2.src = a1; c2.w = packed + kPF2; c2.bias = bias + 32; c2.dst = a2;
-    hipLaunchKernelGGL(k_conv32<kRelu>, grid, blk, 0, s, c2);
+    ConvArgs c2 = c;   // layers 1 and 2 (a1 written for the backward pass)
+    c2.src = recon; c2.w = packed + kPF2; c2.bias = bias + 32; c2.dst = a2;
+    c2.w1 = packed + kPF1; c2.bias1 = bias; c2.dst1 = a1;
+    hipLaunchKernelGGL(k_conv12, grid, blk, 0, s, c2);
     ConvArgs c3 = c;   // layer 3 + loss
     c3.src = a2; c3.w = packed + kPF3; c3.bias = bias + 64; c3.dst = g3; c3.x = recon; c3.orig = orig;
     c3.y_out = y_out; c3.part = part3; c3.gscale = float(2.0 / (double(n) * H * W));
