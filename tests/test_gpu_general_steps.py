@@ -111,3 +111,38 @@ def test_general_step_stream(cuda):
             ref = Co.evaluate(img, M.T6, 10, 5)
             assert int(sse[f, p]) == ref["sse"], (f, p)
             assert np.array_equal(recon[f, o:o + h * w].cpu().numpy().reshape(h, w), ref["rec"])
+
+
+def test_general_step_4k_stream_sampled(cuda):
+    """A step that admits exact halves (T1, step 12) on the benchmark's frame
+    shape (3840 x 2160 4:2:0, r = 10), through the run-time kernels: every
+    plane's squared error of one frame against the oracle, and 300 sampled
+    blocks of a second frame (levels and pixels)."""
+    import torch
+    from synth import video_base_planes, video_frame, video_spec
+    spec = video_spec(n_frames=2)
+    bases = video_base_planes(spec)
+    frames = np.stack([video_frame(spec, bases, f) for f in range(2)])
+    planes = [(o, h, w, w) for (h, w), o in zip(spec.plane_shapes, spec.plane_offsets)]
+    d = _dev(frames, cuda)
+    bpf = A.stream_blocks_per_frame(planes)
+    coef = torch.empty((2, bpf, 10), dtype=torch.int16, device=cuda)
+    recon = torch.empty_like(d)
+    sse = A.evaluate_stream(d, planes, "T1", 10, 12, coef=coef, recon=recon).cpu().numpy()
+    for p, ((h, w), off) in enumerate(zip(spec.plane_shapes, spec.plane_offsets)):
+        ref = Co.evaluate(frames[0, off:off + h * w].reshape(h, w), M.T1, 10, 12)
+        assert int(sse[0, p]) == ref["sse"], p
+    rng = np.random.default_rng(12)
+    coef_h = coef.cpu().numpy()
+    recon_h = recon.cpu().numpy()
+    for _ in range(300):
+        p = int(rng.integers(3))
+        h, w = spec.plane_shapes[p]
+        off = spec.plane_offsets[p]
+        by, bx = int(rng.integers(h // 8)), int(rng.integers(w // 8))
+        blk = frames[1, off:off + h * w].reshape(h, w)[8 * by:8 * by + 8, 8 * bx:8 * bx + 8]
+        ref_b = Co.evaluate(blk, M.T1, 10, 12)
+        b = sum((hh // 8) * (ww // 8) for hh, ww in spec.plane_shapes[:p]) + by * (w // 8) + bx
+        assert np.array_equal(coef_h[1, b], ref_b["coef_int"][0])
+        rb = recon_h[1, off:off + h * w].reshape(h, w)[8 * by:8 * by + 8, 8 * bx:8 * bx + 8]
+        assert np.array_equal(rb, ref_b["rec"])
