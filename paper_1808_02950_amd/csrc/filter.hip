@@ -546,8 +546,12 @@ __device__ __forceinline__ int act_stride(int W) { return 6 * (W + 16) + 8; }
 constexpr uint32_t kOne2 = 0x3f803f80u;   // two bfloat16 ones
 
 // dW2[o][i][t] = sum_p dz2[o][p] a1[i][p + off_t];  db2[o] = sum_p dz2[o][p].
-// Wave w owns the output half oh = w / 2 and input half ih = w % 2 for all 9
-// taps and every pixel of the band, so the four waves write disjoint entries.
+// Wave w owns the input half ih = w % 2 for both output halves and all 9 taps
+// (the activation operands it reads from LDS serve 18 products: 11 LDS reads
+// for 18 MFMAs), over the 32-pixel chunks of parity ph = w / 2.  The two
+// waves of one input half add their sums through LDS in a fixed order, so the
+// partial row is deterministic.
+constexpr int kW2Red = 80;   // floats per lane in the final exchange: 2 x 9 x 4 taps + 2 x 4 bias
 __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     extern __shared__ uint4 smem4[];
     uint16_t *sm = reinterpret_cast<uint16_t *>(smem4);
@@ -555,13 +559,13 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
     uint16_t *dzT = sm, *aT = sm + 32 * DS;
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int oh = wave >> 1, ih = wave & 1;
+    const int ih = wave & 1, ph = wave >> 1;
     for (int c = tid; c < 32 * 6 * 16; c += 256) {
         const int k = c & 15, r = (c >> 4) % 6, sl = c / 96;
         aT[sl * AS + r * AP + (k < 8 ? k : W + k)] = 0;
     }
-    f32x4 acc[9] = {};
-    f32x4 accb = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[2][9] = {};
+    f32x4 accb[2] = {};
     const uint4 ones = {kOne2, kOne2, kOne2, kOne2};
     const int lcpr = a.lw - 5;   // log2 of the 32-pixel chunks per row
     for (int item = int(blockIdx.x); item < a.items; item += int(gridDim.x)) {
@@ -580,31 +584,56 @@ __global__ __launch_bounds__(256) void k_wgrad2(const WgradArgs a) {
             stage_load(sd, a.g, img, y0 + 4 * (sb + 1), 4, a.H, a.lw);
             stage_load(sa, a.act, img, y0 + 4 * (sb + 1) - 1, 6, a.H, a.lw);
         }
-        for (int k = 0; k < (4 << lcpr); ++k) {
+        for (int k = ph; k < (4 << lcpr); k += 2) {
             const int rl = k >> lcpr, px0 = (k & ((1 << lcpr) - 1)) * 32;
-            const uint4 A = lds16(dzT + (16 * oh + n) * DS + rl * W + px0 + 8 * g);
+            const uint4 A0 = lds16(dzT + n * DS + rl * W + px0 + 8 * g);
+            const uint4 A1 = lds16(dzT + (16 + n) * DS + rl * W + px0 + 8 * g);
 #pragma unroll
             for (int dy = 0; dy < 3; ++dy) {
                 const uint16_t *base = aT + (16 * ih + n) * AS + (rl + dy) * AP + 8 + px0 + 8 * g;
                 const uint4 L = lds16(base - 8), M = lds16(base), R = lds16(base + 8);
-                acc[3 * dy + 0] = mma32(A, funnel_l(L, M), acc[3 * dy + 0]);
-                acc[3 * dy + 1] = mma32(A, M, acc[3 * dy + 1]);
-                acc[3 * dy + 2] = mma32(A, funnel_r(M, R), acc[3 * dy + 2]);
+                const uint4 Bl = funnel_l(L, M), Br = funnel_r(M, R);
+                acc[0][3 * dy + 0] = mma32(A0, Bl, acc[0][3 * dy + 0]);
+                acc[1][3 * dy + 0] = mma32(A1, Bl, acc[1][3 * dy + 0]);
+                acc[0][3 * dy + 1] = mma32(A0, M, acc[0][3 * dy + 1]);
+                acc[1][3 * dy + 1] = mma32(A1, M, acc[1][3 * dy + 1]);
+                acc[0][3 * dy + 2] = mma32(A0, Br, acc[0][3 * dy + 2]);
+                acc[1][3 * dy + 2] = mma32(A1, Br, acc[1][3 * dy + 2]);
             }
-            if (ih == 0) accb = mma32(A, ones, accb);
+            if (ih == 0) {
+                accb[0] = mma32(A0, ones, accb[0]);
+                accb[1] = mma32(A1, ones, accb[1]);
+            }
         }
     }
     __syncthreads();   // the next item restages the tiles
     }
+    // pixel-parity halves: ph = 1 hands its sums over, ph = 0 adds them and writes
+    float *red = reinterpret_cast<float *>(smem4) + (ih * 64 + lane) * kW2Red;
+    if (ph == 1) {
+#pragma unroll
+        for (int oh = 0; oh < 2; ++oh) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[(oh * 9 + t) * 4 + i] = acc[oh][t][i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[72 + oh * 4 + i] = accb[oh][i];
+        }
+    }
+    __syncthreads();
+    if (ph == 1) return;
     float *dst = a.part + int64_t(blockIdx.x) * kParams;
     const int ii = slot_channel(16 * ih + n);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int o = slot_channel(16 * oh + 4 * g + i);
+    for (int oh = 0; oh < 2; ++oh)
 #pragma unroll
-        for (int t = 0; t < 9; ++t) dst[kOffW2 + (o * 32 + ii) * 9 + t] = acc[t][i];
-        if (ih == 0 && n == 0) dst[kOffB2 + o] = accb[i];
-    }
+        for (int i = 0; i < 4; ++i) {
+            const int o = slot_channel(16 * oh + 4 * g + i);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) dst[kOffW2 + (o * 32 + ii) * 9 + t] = acc[oh][t][i] + red[(oh * 9 + t) * 4 + i];
+            if (ih == 0 && n == 0) dst[kOffB2 + o] = accb[oh][i] + red[72 + oh * 4 + i];
+        }
 }
 
 // dW1[o][t] = sum_p dz1[o][p] xn[p + off_t] (B column t < 9), db1 (column 9 = ones)
@@ -1188,7 +1217,8 @@ WsLayout layout(int n, int H, int W) {
 size_t wgrad_lds(int W) {
     const size_t stage2 = size_t(32 * (4 * W + 8) + 32 * (6 * (W + 16) + 8)) * 2;        // wgrad2
     const size_t stage13 = size_t(32 * (kSb1 * W + 8) + (kSb1 + 2) * (W + 16)) * 2;      // wgrad1, wgrad3
-    return std::max(std::max(stage2, stage13), size_t(32 * 10) * 4);
+    const size_t red2 = size_t(2 * 64 * kW2Red) * 4;                                       // wgrad2's exchange
+    return std::max(std::max(std::max(stage2, stage13), size_t(32 * 10) * 4), red2);
 }
 
 // Adam's bias corrections for a step (host side, float64)
