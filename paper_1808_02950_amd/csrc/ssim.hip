@@ -4,7 +4,7 @@
 // unit sum) at every position where the window fits, C1 = (0.01 * 255)^2,
 // C2 = (0.03 * 255)^2, and the mean of the map per plane.
 //
-// One wave computes a tile of the map: 64 output columns (one per lane) x 88
+// One wave computes a tile of the map: 64 output columns (one per lane) x 176
 // output rows.  Input rows stream through it once: each row's two pixels per
 // position (loaded one row ahead) go to a per-wave LDS row (x | y << 16),
 // every lane sums its 11
@@ -29,7 +29,7 @@ namespace adct {
 namespace {
 
 constexpr int kWin = 11;
-constexpr int kTileRows = 88;                 // output rows per tile (a multiple of 11)
+constexpr int kTileRows = 176;                // output rows per tile (a multiple of 11)
 constexpr double kC1 = 6.5025;                // (0.01 * 255)^2
 constexpr double kC2 = 58.5225;               // (0.03 * 255)^2
 constexpr double kFix = 68719476736.0;        // 2^36
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_ssim(const SsimArgs a) {
         ssim_row<9>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
         ssim_row<10>(a, rb, tb, P, r0, i0, nout, ca, cb, lane, row, nx, acc, sum, col_ok);
     }
-    // fixed point (|map| <= 1, at most 88 entries per lane), then the wave sum
+    // fixed point (|map| <= 1, at most 176 entries per lane: below 2^44), then the wave sum
     long long v = llrint(sum * kFix);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -32,7 +32,8 @@ def _pair(h, w, seed, noise=12):
 
 
 @pytest.mark.parametrize("h,w", [(11, 11), (11, 75), (75, 11), (99, 74), (98, 75), (37, 45),
-                                 (64, 200), (200, 150), (181, 267)])
+                                 (64, 200), (200, 150), (181, 267), (186, 75), (187, 74),
+                                 (363, 65)])
 def test_ssim_matches_oracle(cuda, h, w):
     x, y = _pair(h, w, seed=h * 1000 + w)
     got = float(A.ssim(_dev(x, cuda), _dev(y, cuda), None).cpu().numpy()[0, 0])
