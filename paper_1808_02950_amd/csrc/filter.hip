@@ -794,13 +794,15 @@ __global__ __launch_bounds__(256) void k_wgrad3(const WgradArgs a) {
 }
 
 // fixed-order sums over workgroups: deterministic gradient and loss.  Blocks
-// below kRedParamBlocks take 64 consecutive weight-gradient entries (256
-// contiguous bytes of every partial row); their 4 row groups each sum every
-// 4th partial row (16 loads of a thread in flight together) and the group sums
-// are added in a fixed order.  The last two
-// blocks sum the per-wave partials of the loss-gradient kernel (b3's gradient,
-// then the loss) with all 256 threads and a fixed-order tree.
-constexpr int kRedCols = 64, kRedGroups = 4;
+// below kRedParamBlocks take kRedCols consecutive weight-gradient entries (128
+// contiguous bytes of every partial row); their kRedGroups row groups each sum
+// every kRedGroups-th partial row, with up to 16 loads of a thread in flight
+// together (one round at 512 partial rows), and the group sums are added in a
+// fixed order.  The last two blocks sum the per-wave partials of the
+// loss-gradient kernel (b3's gradient, then the loss) with all threads and a
+// fixed-order tree.
+constexpr int kRedThreads = 1024;
+constexpr int kRedCols = 32, kRedGroups = kRedThreads / kRedCols;
 constexpr int kRedParamBlocks = (kOffB3 + kRedCols - 1) / kRedCols;
 
 // Adam's state and hyper-parameters (c1, c2: the bias corrections of the step)
@@ -819,19 +821,19 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, int i, float g) {
 
 // ADAM: the thread that completes a gradient entry also applies the update
 template <bool ADAM>
-__global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part, int n_wg,
-                                                const float *__restrict__ part3, int n_w3, float inv_count,
-                                                float *__restrict__ grad, float *__restrict__ loss,
-                                                const AdamArgs ad) {
-    __shared__ float sm[256];
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const float *__restrict__ part, int n_wg,
+                                                        const float *__restrict__ part3, int n_w3, float inv_count,
+                                                        float *__restrict__ grad, float *__restrict__ loss,
+                                                        const AdamArgs ad) {
+    __shared__ float sm[kRedThreads];
     const int tid = threadIdx.x;
     if (int(blockIdx.x) >= kRedParamBlocks) {
         const int k = int(blockIdx.x) == kRedParamBlocks ? 1 : 0;   // 1: b3 gradient, 0: loss
         float s = 0.f;
-        for (int w = tid; w < n_w3; w += 256) s += part3[2 * w + k];
+        for (int w = tid; w < n_w3; w += kRedThreads) s += part3[2 * w + k];
         sm[tid] = s;
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
+        for (int h = kRedThreads / 2; h > 0; h >>= 1) {
             if (tid < h) sm[tid] += sm[tid + h];
             __syncthreads();
         }
@@ -1292,10 +1294,10 @@ adct_status launch_grad(const float *params, const uint8_t *recon, const uint8_t
     hipLaunchKernelGGL(k_wgrad1, dim3(L.n_wg), blk, lds, s, w1);
     const float inv_count = float(1.0 / (double(n) * H * W));
     if (adam)
-        hipLaunchKernelGGL(k_reduce<true>, dim3(kRedParamBlocks + 2), blk, 0, s, part, L.n_wg, part3, L.n_w3,
+        hipLaunchKernelGGL(k_reduce<true>, dim3(kRedParamBlocks + 2), dim3(kRedThreads), 0, s, part, L.n_wg, part3, L.n_w3,
                            inv_count, grad, loss, *adam);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(kRedParamBlocks + 2), blk, 0, s, part, L.n_wg, part3, L.n_w3,
+        hipLaunchKernelGGL(k_reduce<false>, dim3(kRedParamBlocks + 2), dim3(kRedThreads), 0, s, part, L.n_wg, part3, L.n_w3,
                            inv_count, grad, loss, AdamArgs{});
     ADCT_HIP(hipGetLastError());
     return ADCT_OK;
