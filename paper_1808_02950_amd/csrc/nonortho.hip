@@ -5,14 +5,19 @@
 // Decoder: for T without orthogonal rows the transpose is no inverse, and the
 // reconstruction is A = C_hat^-1 B' C_hat^-T.  With C_hat = S T (S diagonal) and
 // zonal coding B' = S Y' S, this is T^-1 Y' T^-T = adj(T) Y' adj(T)^T / det(T)^2:
-// the kernel computes the numerator in float64 on integers (exact below 2^53,
-// bounded on the host) and divides exactly, so the pixels are bit-exact.
-// One lane owns one 8x8 block for the whole pipeline.
+// with adj(T) and det(T) first divided by their common factor, so the signed
+// DCT and BAS-2008b reconstruct over 8^2 instead of 2048^2 and 1024^2.  Where
+// that denominator is a power of two and the numerators stay below 2^24 (both
+// of those matrices) every step is exact in float32 and one conversion rounds
+// and saturates; otherwise the kernel computes the numerator in float64 on
+// integers (exact below 2^53, bounded on the host) and divides exactly.  Either way the pixels
+// are bit-exact.  One lane owns one 8x8 block for the whole pipeline.
 #include <string.h>
 
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <numeric>
 #include <vector>
 
 #include "adct_internal.hpp"
@@ -34,9 +39,13 @@ struct InvArgs {
     int64_t fs_in, fs_out;
     int32_t n_frames, n_planes, waves_per_frame, r;
     int32_t T[64];         // T[8k + m]
-    double adj[64];        // adj(T)[8x + k]
-    double den;            // det(T)^2
+    double adj[64];        // adj(T)[8x + k] / g (g: the common factor of adj(T) and det(T))
+    double den;            // (det(T) / g)^2
     double inv_den;
+    int8_t T8[64];         // exact float32 form: T as bytes (four a scalar register)
+    float adj_f[64];       //   the reduced adj(T)
+    int32_t yoff[64];      //   128 (sum_m T[k][m]) (sum_m T[l][m]): Y minus Y of the pixels - 128
+    float inv_den_f;       //   1 / den = 2^-e
     InvPlane pl[kMaxPlanes];
 };
 
@@ -154,6 +163,161 @@ __global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
             acc_fp = fp;
         }
         acc += wave_sum(e);
+    }
+    if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
+}
+
+// ------------------------------------------------------------------ exact float32 form
+//
+// For den = 2^e with every numerator below 2^24 in magnitude (the signed DCT
+// and BAS-2008b after the common factor is divided out): Y / den, its products
+// with adj and their sums are multiples of 2^-e below 2^24 2^-e, so float32
+// holds every step exactly, and the pixel is one conversion that rounds half
+// to even and saturates to [0, 255].
+
+struct InvBlock {
+    int f, p;
+    bool active;
+    int64_t off;           // byte offset of the block's top-left pixel inside a frame
+};
+
+__device__ __forceinline__ InvBlock inv_block_of(const InvArgs &a, int gw, int lane) {
+    InvBlock B;
+    B.f = gw / a.waves_per_frame;
+    const int w = gw - B.f * a.waves_per_frame;
+    int p = 0;
+    while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
+    B.p = p;
+    const InvPlane &P = a.pl[p];
+    const int blk = (w - P.wave_start) * 64 + lane;
+    B.active = blk < P.nblocks;
+    const int b = B.active ? blk : 0;       // idle lanes read block 0 of the plane
+    const int by = b / P.nbx, bx = b - by * P.nbx;
+    B.off = P.off + int64_t(8 * by) * P.pitch + 8 * bx;
+    return B;
+}
+
+__device__ __forceinline__ void inv_load(const InvArgs &a, const InvBlock &B, uint32_t (&pix)[8][2]) {
+    const int pitch = a.pl[B.p].pitch;
+    const uint8_t *src = a.in + int64_t(B.f) * a.fs_in + B.off;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const u32x2 v = __builtin_nontemporal_load((const u32x2 *)(src + int64_t(x) * pitch));
+        pix[x][0] = v.x;
+        pix[x][1] = v.y;
+    }
+}
+
+template <int BAND>
+__device__ __forceinline__ void inv_int_block(const InvArgs &a, const InvBlock &B, const uint32_t (&pix)[8][2],
+                                              unsigned long long &acc, int &acc_fp) {
+    constexpr int KB = BAND + 1 < 8 ? BAND + 1 : 8;
+    const int lane = threadIdx.x & 63;
+    // Y = T A T^T, then the zig-zag prefix.  The row pass takes the pixels
+    // minus 128 as signed bytes, four products per signed dot instruction
+    // against a packed row of T; the constant the offset adds to Y is yoff.
+    const int32_t *tpk = reinterpret_cast<const int32_t *>(a.T8);
+    int Z[8][KB];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const int p0 = int(pix[x][0] ^ 0x80808080u), p1 = int(pix[x][1] ^ 0x80808080u);
+#pragma unroll
+        for (int l = 0; l < KB; ++l)
+            Z[x][l] = __builtin_amdgcn_sdot4(tpk[2 * l + 1], p1, __builtin_amdgcn_sdot4(tpk[2 * l], p0, 0, false),
+                                             false);
+    }
+    int Y[KB][KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+#pragma unroll
+        for (int l = 0; l < KB; ++l) {
+            int s = 0;
+            if (k + l <= BAND) {
+                s = a.yoff[8 * k + l];
+#pragma unroll
+                for (int x = 0; x < 8; ++x) s += __mul24(int(a.T8[8 * k + x]), Z[x][l]);
+            }
+            Y[k][l] = (k + l <= BAND && zz_pos(k, l) < a.r) ? s : 0;
+        }
+    // (adj Y' adj^T) / den row by row in exact float32
+    float Yf[KB][KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+#pragma unroll
+        for (int l = 0; l < KB; ++l) Yf[k][l] = (k + l <= BAND) ? float(Y[k][l]) * a.inv_den_f : 0.f;
+    uint8_t *dst = a.out ? a.out + int64_t(B.f) * a.fs_out + B.off : nullptr;
+    const int pitch = a.pl[B.p].pitch;
+    uint32_t sq = 0, cross = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        float U[KB];
+#pragma unroll
+        for (int l = 0; l < KB; ++l) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                if (k + l <= BAND) s = fmaf(a.adj_f[8 * x + k], Yf[k][l], s);
+            U[l] = s;
+        }
+        uint32_t w[2] = {0u, 0u};
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            float s = 0.f;
+#pragma unroll
+            for (int l = 0; l < KB; ++l) s = fmaf(U[l], a.adj_f[8 * y + l], s);
+            w[y >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(s, uint32_t(y & 3), w[y >> 2]);
+        }
+        u32x2 v;
+        v.x = w[0];
+        v.y = w[1];
+        sq = __builtin_amdgcn_udot4(v.x, v.x, sq, false);
+        sq = __builtin_amdgcn_udot4(v.y, v.y, sq, false);
+        sq = __builtin_amdgcn_udot4(pix[x][0], pix[x][0], sq, false);
+        sq = __builtin_amdgcn_udot4(pix[x][1], pix[x][1], sq, false);
+        cross = __builtin_amdgcn_udot4(v.x, pix[x][0], cross, false);
+        cross = __builtin_amdgcn_udot4(v.y, pix[x][1], cross, false);
+        if (B.active && dst) __builtin_nontemporal_store(v, (u32x2 *)(dst + int64_t(x) * pitch));
+    }
+    // sum (q - a)^2 = sum q^2 + sum a^2 - 2 sum q a (exact modulo 2^32, below it)
+    const unsigned e = B.active ? sq - 2u * cross : 0u;
+    const int fp = B.f * a.n_planes + B.p;
+    if (fp != acc_fp) {
+        if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
+        acc = 0;
+        acc_fp = fp;
+    }
+    acc += wave_sum(e);
+}
+
+// Persistent grid; each wave loads its next 64 blocks before it transforms
+// the current ones (on every pass: the last pass re-reads its own blocks).
+template <int BAND>
+__global__ __launch_bounds__(256) void k_inverse_int(const InvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int total = a.n_frames * a.waves_per_frame;
+    const int stride = int(gridDim.x) * 4;
+    int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (gw >= total) return;
+    unsigned long long acc = 0;
+    int acc_fp = -1;
+    uint32_t pa[8][2], pb[8][2];
+    InvBlock ba = inv_block_of(a, gw, lane), bb = ba;
+    inv_load(a, ba, pa);
+    while (true) {
+        int nxt = gw + stride;
+        bool more = nxt < total;                  // wave-uniform
+        bb = inv_block_of(a, more ? nxt : gw, lane);
+        inv_load(a, bb, pb);
+        inv_int_block<BAND>(a, ba, pa, acc, acc_fp);
+        if (!more) break;
+        gw = nxt;
+        nxt = gw + stride;
+        more = nxt < total;
+        ba = inv_block_of(a, more ? nxt : gw, lane);
+        inv_load(a, ba, pa);
+        inv_int_block<BAND>(a, bb, pb, acc, acc_fp);
+        if (!more) break;
+        gw = nxt;
     }
     if (acc_fp >= 0 && acc && lane == 0) atomicAdd(a.sse + acc_fp, acc);
 }
@@ -280,6 +444,11 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     const int ad = adjugate_det(T, adj, &det);
     if (ad == 1) return fail(ADCT_EINVAL, "T is singular");
     if (ad == 2) return fail(ADCT_EOVERFLOW, "T is too large for exact float64 numerators");
+    // T^-1 = adj / det: divide out the common factor of all entries and det
+    int64_t g = det < 0 ? -det : det;
+    for (int i = 0; i < 64; ++i) g = std::gcd(g, adj[i] < 0 ? -adj[i] : adj[i]);
+    for (int i = 0; i < 64; ++i) adj[i] /= g;
+    det /= g;
     // numerator bound: |adj Y' adj^T| <= (sum |adj|)^2 max|Y| per entry
     int64_t rowsum = 0, tsum = 0;
     for (int k = 0; k < 8; ++k) {
@@ -301,6 +470,22 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     }
     a.den = double(det) * double(det);
     a.inv_den = 1.0 / a.den;
+    // the exact float32 form: den a power of two, every numerator (Y, the row
+    // sums U, the pixel sums) below 2^24; Y in int32 products of 24-bit operands
+    const int64_t den = det * det;
+    const int64_t ymax_i = 255 * tsum * tsum, umax = rowsum * ymax_i, smax = rowsum * umax;
+    const bool int_form = (den & (den - 1)) == 0 && smax < (int64_t(1) << 24) && umax < (int64_t(1) << 24) &&
+                          ymax_i < (int64_t(1) << 23);
+    if (int_form) {
+        int rs[8] = {};
+        for (int i = 0; i < 64; ++i) {
+            a.T8[i] = T[i];
+            a.adj_f[i] = float(adj[i]);
+            rs[i / 8] += T[i];
+        }
+        for (int i = 0; i < 64; ++i) a.yoff[i] = 128 * rs[i / 8] * rs[i % 8];
+        a.inv_den_f = float(1.0 / double(den));
+    }
     a.in = frames;
     a.out = recon;
     a.sse = reinterpret_cast<unsigned long long *>(sse);
@@ -333,7 +518,8 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     ADCT_HIP(hipGetDevice(&dev));
     ADCT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     // r <= 10 keeps only coefficients with k + l <= 3
-    auto kern = r <= 10 ? k_inverse_codec<3> : k_inverse_codec<14>;
+    auto kern = int_form ? (r <= 10 ? k_inverse_int<3> : k_inverse_int<14>)
+                         : (r <= 10 ? k_inverse_codec<3> : k_inverse_codec<14>);
     ADCT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
     const int64_t want = (waves * n_frames + 3) / 4;
     const int grid = int(std::min<int64_t>(want, int64_t(std::max(per_cu, 1)) * cus));

@@ -352,7 +352,7 @@ def test_inverse_codec_argument_errors_host_only():
     h = np.array([[1]])
     for _ in range(3):
         h = np.block([[h, h], [h, -h]])                        # 8 x 8 Hadamard
-    big = (ctypes.c_int8 * 64)(*[int(v) for v in (120 * h).ravel()])
+    big = (ctypes.c_int8 * 64)(*[int(v) for v in (127 * h).ravel()])   # Y passes 2^31 / 8
     assert call(T=big) == -4
 
 

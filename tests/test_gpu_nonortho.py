@@ -43,6 +43,34 @@ def test_inverse_decoder_matches_oracle(cuda, name, shape, r):
     assert np.array_equal(rec, want["rec"]) and sse == want["sse"]
 
 
+def _hadamard8():
+    h = np.array([[1]])
+    for _ in range(3):
+        h = np.block([[h, h], [h, -h]])
+    return h
+
+
+@pytest.mark.parametrize("which", ["2H", "unimodular", "wide"])
+def test_inverse_decoder_other_denominators(cuda, which):
+    """Matrices whose reduced denominator takes each form: 2 H_8 (T^-1 = H_8 / 16,
+    den 256 after the common factor of adj and det is divided out), a unimodular
+    T (den 1: every reconstruction an integer), and one with entries up to 9
+    whose numerators need the float64 form."""
+    if which == "2H":
+        t = 2 * _hadamard8()
+    elif which == "unimodular":
+        t = np.eye(8, dtype=np.int64) + np.tril(np.ones((8, 8), dtype=np.int64), -1) * \
+            np.array([1, -1, 0, 1, -1, 1, 0, -1])[None, :]
+    else:
+        t = np.array(M.t_sdct(), dtype=np.int64) * np.array([1, 1, 3, 1, 9, 1, 3, 1])[:, None]
+    assert round(abs(np.linalg.det(t))) >= 1
+    for shape, r in (((64, 72), 10), ((40, 48), 40)):
+        img = ar1_image(*shape, rho=0.9, seed=shape[0] + r)
+        rec, sse = _run(img, t.astype(np.int8), r, cuda)
+        want = N.evaluate(img, t, r)
+        assert np.array_equal(rec, want["rec"]) and sse == want["sse"], (which, r)
+
+
 @pytest.mark.parametrize("name", ["T1", "LO", "T6"])
 def test_inverse_decoder_on_orthogonal_equals_the_codec(cuda, name):
     img = ar1_image(96, 128, rho=0.95, seed=7)
