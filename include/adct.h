@@ -294,7 +294,9 @@ adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t frame_stride
  * of Sec. 6.1.1 holds for orthogonal rows only), rounded half to even and
  * clipped; squared errors per (frame, plane).  The reconstruction equals
  * adj(T) Y' adj(T)^T / det(T)^2 with Y' the kept integer stage and is computed
- * exactly.  frames / planes / recon / frame strides as in adct_evaluate_stream
+ * exactly, after adj(T) and det(T) are divided by their common factor (in
+ * float32 where that leaves a power-of-two denominator and numerators below
+ * 2^24, as for the signed DCT and BAS-2008b; in float64 otherwise).  frames / planes / recon / frame strides as in adct_evaluate_stream
  * (H, W multiples of 8).  T: host int8 [64] row-major.  sse: device uint64
  * [n_frames][n_planes], 8-byte aligned, zeroed by the call then accumulated;
  * recon nullable.  No quantiser (the paper's image experiment is zonal).
@@ -302,7 +304,8 @@ adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t frame_stride
  * not in [1, 64], n_frames < 1, n_planes not in [1, 4], too many blocks;
  * ADCT_EDIM a plane not a positive multiple of 8, pitch < W, negative offset,
  * unaligned sse, non-positive frame stride with several frames; ADCT_EOVERFLOW
- * T whose exact numerators would pass 2^53. */
+ * T whose exact numerators (after the common factor) would pass 2^53, or whose
+ * integer stage Y would pass 2^31 / 8. */
 adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t frame_stride, int n_frames,
                                   const adct_plane *planes, int n_planes, const int8_t *T, int r,
                                   uint8_t *recon, int64_t frame_stride_out, uint64_t *sse,
