@@ -310,7 +310,7 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
                 // zero if it went towards it: m + 1/2 = Y / dd for Y > 0, m - 1/2 =
                 // Y / dd for Y < 0
                 int m = __double2loint(fma(double(q), cc.sk[ck], 6755399441055744.0));
-                const int t1 = (2 * m + 1) * cc.dd[ck];
+                const int t1 = __mul24(2 * m + 1, cc.dd[ck]);   // both below 2^23
                 const int t2 = t1 - 2 * cc.dd[ck];
                 m += (q > 0 && 2 * q == t1) ? 1 : 0;
                 m -= (q < 0 && 2 * q == t2) ? 1 : 0;

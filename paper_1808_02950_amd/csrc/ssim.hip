@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include "adct_internal.hpp"
+#include "xcd.hpp"
 
 namespace adct {
 namespace {
@@ -130,16 +131,9 @@ __device__ __forceinline__ void ssim_row(const SsimArgs &a, const uint8_t *rb, c
     }
 }
 
-// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b % 8),
-// each with its own L2.  Renumbering them so that every XCD takes one
-// contiguous run of tiles puts horizontally adjacent strips, which share the
-// 128-byte lines at their seams, on the same L2 at about the same time.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
-    const int x = b % kXcds, i = b / kXcds, q = nb / kXcds, r = nb % kXcds;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
-
+// Workgroups are renumbered so that each XCD takes one contiguous run of
+// tiles: horizontally adjacent strips, which share the 128-byte lines at their
+// seams, then run on the same L2 at about the same time.
 __global__ __launch_bounds__(256) void k_ssim(const SsimArgs a) {
     __shared__ uint32_t rows[4][64 + kWin - 1];
     const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
