@@ -142,6 +142,8 @@ struct JamPlane {
     int32_t tpr;          // tiles per block-row
     int32_t tile_start;   // first tile of the plane inside a frame
     int32_t block_off;    // first block of the plane inside a frame
+    uint32_t tpr_m;       // i / tpr = umulhi(i, tpr_m) >> tpr_s (magic_u31)
+    int32_t tpr_s;
 };
 
 struct JamArgs {
@@ -152,6 +154,8 @@ struct JamArgs {
     int64_t fs_in, fs_out;
     int32_t n_frames, n_planes;
     int32_t tiles_per_frame, blocks_per_frame;
+    uint32_t tpf_m;       // g / tiles_per_frame by multiply-high (magic_u31)
+    int32_t tpf_s;
     int32_t r, band;      // prefix length, the last anti-diagonal it reaches (at most N - 1)
     int32_t step;
     double inv_step;
@@ -189,16 +193,25 @@ struct JTile {
     int f, p, by, tx;     // frame, plane, block-row, tile inside the block-row
 };
 
+// n / d for 0 <= n < 2^31 from the magic pair of a wave-uniform d
+__device__ __forceinline__ int udiv_magic(int n, uint32_t m, int s) {
+    return s < 0 ? n : int(__umulhi(uint32_t(n), m) >> s);
+}
+
+// g is wave-uniform, and so is everything here: multiply-high divisions by
+// host-computed magic numbers keep the walk on the scalar unit.
 __device__ __forceinline__ JTile jtile_of(const JamArgs &a, int g) {
     JTile t;
-    t.f = g / a.tiles_per_frame;
-    const int w = g - t.f * a.tiles_per_frame;
+    // (the readfirstlanes keep the values scalar where the compiler has moved
+    // kernel arguments to vector registers)
+    t.f = __builtin_amdgcn_readfirstlane(udiv_magic(g, a.tpf_m, a.tpf_s));
+    const int w = __builtin_amdgcn_readfirstlane(g - t.f * a.tiles_per_frame);
     int p = 0;
     while (p + 1 < a.n_planes && w >= a.pl[p + 1].tile_start) ++p;
-    t.p = p;
-    const JamPlane &P = a.pl[p];
+    t.p = __builtin_amdgcn_readfirstlane(p);
+    const JamPlane &P = a.pl[t.p];
     const int i = w - P.tile_start;
-    t.by = i / P.tpr;
+    t.by = __builtin_amdgcn_readfirstlane(udiv_magic(i, P.tpr_m, P.tpr_s));
     t.tx = i - t.by * P.tpr;
     return t;
 }
@@ -233,8 +246,10 @@ __device__ __forceinline__ JRow<N> jrow_of(const JamArgs &a, int g, int b, int j
 template <int N>
 __device__ __forceinline__ void load_row(const JamArgs &a, const JRow<N> &r, uint32_t (&pix)[N / 4]) {
     const JamPlane &Pl = a.pl[r.p];
+    // a wave-uniform plane base and a 32-bit offset inside the plane (the host
+    // bounds H, the pitch and the plane size)
     const uint8_t *src = a.in + int64_t(r.f) * a.fs_in + Pl.in_off +
-                         int64_t(min(r.y, Pl.H - 1)) * Pl.pitch_in;
+                         __umul24(uint32_t(min(r.y, Pl.H - 1)), uint32_t(Pl.pitch_in));
     if (r.full) {
 #pragma unroll
         for (int v = 0; v < N / 16; ++v) {
@@ -366,7 +381,8 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
         }
         e = sq - 2u * cross;
         if (a.out) {
-            uint8_t *dst = a.out + int64_t(rw.f) * a.fs_out + Pl.out_off + int64_t(rw.y) * Pl.pitch_out + rw.x0;
+            uint8_t *dst = a.out + int64_t(rw.f) * a.fs_out + Pl.out_off +
+                           (__umul24(uint32_t(rw.y), uint32_t(Pl.pitch_out)) + uint32_t(rw.x0));
             if (rw.full) {
 #pragma unroll
                 for (int v = 0; v < NW / 4; ++v) {
@@ -559,6 +575,8 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
         const adct_plane &q = planes[p];
         if (q.H < 1 || q.W < 1 || q.pitch < q.W || q.offset < 0)
             return fail(ADCT_EDIM, "each plane needs H, W >= 1, pitch >= W and offset >= 0");
+        if (q.H >= (1 << 24) || q.pitch >= (1 << 24) || int64_t(q.H) * q.pitch >= (int64_t(1) << 31))
+            return fail(ADCT_ERANGE, "planes are limited to H, pitch < 2^24 and H * pitch < 2^31");
         JamPlane &d = a.pl[p];
         d.in_off = q.offset;
         d.out_off = q.offset;
@@ -570,6 +588,7 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
         d.tpr = (d.nbx + WB - 1) / WB;
         d.tile_start = int32_t(tiles);
         d.block_off = int32_t(blocks);
+        magic_u31(uint32_t(d.tpr), &d.tpr_m, &d.tpr_s);
         const int64_t nby = (q.H + N - 1) / N;
         tiles += nby * d.tpr;
         blocks += nby * d.nbx;
@@ -580,6 +599,7 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
         return fail(ADCT_ERANGE, "too many blocks in one call");
     a.tiles_per_frame = int32_t(tiles);
     a.blocks_per_frame = int32_t(blocks);
+    magic_u31(uint32_t(tiles), &a.tpf_m, &a.tpf_s);
     a.r = r;
     // last anti-diagonal reached by the prefix of length r
     int band = 0, cnt = 0;
