@@ -276,8 +276,9 @@ adct_status adct_jam_matrix(adct_transform_id base, int N, int8_t *T, int32_t *n
  * Errors: ADCT_EINVAL null frames / planes / sse; ADCT_ENOTSUP base other than
  * ADCT_T1, quant_step not a multiple of N; ADCT_ERANGE N not 16 or 32, r not in
  * [1, N * N], quant_step not in [0, 4096], n_frames < 1, n_planes not in [1, 4],
- * too many blocks; ADCT_EDIM H or W < 1, pitch < W, negative offset, unaligned
- * sse or coef, non-positive frame stride with several frames. */
+ * a plane with H or pitch >= 2^24 or H * pitch >= 2^31, too many blocks;
+ * ADCT_EDIM H or W < 1, pitch < W, negative offset, unaligned sse or coef,
+ * non-positive frame stride with several frames. */
 adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t frame_stride, int n_frames,
                                      const adct_plane *planes, int n_planes,
                                      adct_transform_id base, int N, int r, int quant_step,
