@@ -326,6 +326,10 @@ def test_jam_argument_errors_host_only():
     assert call(planes=A.planes_struct([(-1, 40, 40, 40)])) == -2
     assert call(sse=ctypes.c_void_p(8196)) == -2
     assert call(coef=ctypes.c_void_p(4098)) == -2
+    # 32-bit in-plane offsets: H and pitch below 2^24, the plane below 2^31 bytes
+    assert call(planes=A.planes_struct([(0, 1 << 24, 40, 40)])) == -3
+    assert call(planes=A.planes_struct([(0, 40, 40, 1 << 24)])) == -3
+    assert call(planes=A.planes_struct([(0, 1 << 17, 40, 1 << 14)])) == -3
 
 
 def test_inverse_codec_argument_errors_host_only():
