@@ -302,7 +302,8 @@ adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t frame_stride
  * [n_frames][n_planes], 8-byte aligned, zeroed by the call then accumulated;
  * recon nullable.  No quantiser (the paper's image experiment is zonal).
  * Errors: ADCT_EINVAL null frames / planes / T / sse, T singular; ADCT_ERANGE r
- * not in [1, 64], n_frames < 1, n_planes not in [1, 4], too many blocks;
+ * not in [1, 64], n_frames < 1, n_planes not in [1, 4], a plane with H or pitch
+ * >= 2^24 or H * pitch >= 2^31, too many blocks;
  * ADCT_EDIM a plane not a positive multiple of 8, pitch < W, negative offset,
  * unaligned sse, non-positive frame stride with several frames; ADCT_EOVERFLOW
  * T whose exact numerators (after the common factor) would pass 2^53, or whose

@@ -30,6 +30,8 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 struct InvPlane {
     int64_t off;
     int32_t pitch, nbx, nblocks, wave_start;
+    uint32_t nbx_m;        // b / nbx = umulhi(b, nbx_m) >> nbx_s (magic_u31)
+    int32_t nbx_s;
 };
 
 struct InvArgs {
@@ -38,6 +40,8 @@ struct InvArgs {
     unsigned long long *sse;
     int64_t fs_in, fs_out;
     int32_t n_frames, n_planes, waves_per_frame, r;
+    uint32_t wpf_m;        // gw / waves_per_frame by multiply-high (magic_u31)
+    int32_t wpf_s;
     int32_t T[64];         // T[8k + m]
     double adj[64];        // adj(T)[8x + k] / g (g: the common factor of adj(T) and det(T))
     double den;            // (det(T) / g)^2
@@ -181,19 +185,28 @@ struct InvBlock {
     int64_t off;           // byte offset of the block's top-left pixel inside a frame
 };
 
+// n / d for 0 <= n < 2^31 from the magic pair of d
+__device__ __forceinline__ int udiv_magic(int n, uint32_t m, int s) {
+    return s < 0 ? n : int(__umulhi(uint32_t(n), m) >> s);
+}
+
+// The frame, plane and first block are wave-uniform and stay on the scalar
+// unit (multiply-high divisions by host-computed magic numbers); a lane's
+// block row is one more multiply-high, its offset inside the plane 32 bits
+// (the host bounds H and the pitch below 2^24 and a plane below 2^31 bytes).
 __device__ __forceinline__ InvBlock inv_block_of(const InvArgs &a, int gw, int lane) {
     InvBlock B;
-    B.f = gw / a.waves_per_frame;
-    const int w = gw - B.f * a.waves_per_frame;
+    B.f = __builtin_amdgcn_readfirstlane(udiv_magic(gw, a.wpf_m, a.wpf_s));
+    const int w = __builtin_amdgcn_readfirstlane(gw - B.f * a.waves_per_frame);
     int p = 0;
     while (p + 1 < a.n_planes && w >= a.pl[p + 1].wave_start) ++p;
-    B.p = p;
-    const InvPlane &P = a.pl[p];
+    B.p = __builtin_amdgcn_readfirstlane(p);
+    const InvPlane &P = a.pl[B.p];
     const int blk = (w - P.wave_start) * 64 + lane;
     B.active = blk < P.nblocks;
     const int b = B.active ? blk : 0;       // idle lanes read block 0 of the plane
-    const int by = b / P.nbx, bx = b - by * P.nbx;
-    B.off = P.off + int64_t(8 * by) * P.pitch + 8 * bx;
+    const int by = udiv_magic(b, P.nbx_m, P.nbx_s), bx = b - by * P.nbx;
+    B.off = P.off + (__umul24(uint32_t(8 * by), uint32_t(P.pitch)) + uint32_t(8 * bx));
     return B;
 }
 
@@ -499,10 +512,13 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
         const adct_plane &q = planes[p];
         if (q.H < 8 || q.W < 8 || (q.H & 7) || (q.W & 7) || q.pitch < q.W || q.offset < 0)
             return fail(ADCT_EDIM, "each plane needs H, W positive multiples of 8, pitch >= W, offset >= 0");
+        if (q.H >= (1 << 24) || q.pitch >= (1 << 24) || int64_t(q.H) * q.pitch >= (int64_t(1) << 31))
+            return fail(ADCT_ERANGE, "planes are limited to H, pitch < 2^24 and H * pitch < 2^31");
         InvPlane &d = a.pl[p];
         d.off = q.offset;
         d.pitch = q.pitch;
         d.nbx = q.W / 8;
+        magic_u31(uint32_t(d.nbx), &d.nbx_m, &d.nbx_s);
         d.nblocks = (q.H / 8) * (q.W / 8);
         d.wave_start = int32_t(waves);
         waves += (d.nblocks + 63) / 64;
@@ -510,6 +526,7 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     }
     if (waves * n_frames > (int64_t(1) << 31) - 1) return fail(ADCT_ERANGE, "too many blocks in one call");
     a.waves_per_frame = int32_t(waves);
+    magic_u31(uint32_t(waves), &a.wpf_m, &a.wpf_s);
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     const int nz = n_frames * n_planes;
     hipLaunchKernelGGL(k_inv_zero, dim3((nz + 255) / 256), dim3(256), 0, hs, a.sse, nz);

@@ -358,6 +358,10 @@ def test_inverse_codec_argument_errors_host_only():
         h = np.block([[h, h], [h, -h]])                        # 8 x 8 Hadamard
     big = (ctypes.c_int8 * 64)(*[int(v) for v in (127 * h).ravel()])   # Y passes 2^31 / 8
     assert call(T=big) == -4
+    # 32-bit in-plane offsets: H and pitch below 2^24, the plane below 2^31 bytes
+    assert call(planes=A.planes_struct([(0, 1 << 24, 16, 16)])) == -3
+    assert call(planes=A.planes_struct([(0, 16, 16, 1 << 24)])) == -3
+    assert call(planes=A.planes_struct([(0, 1 << 17, 16, 1 << 14)])) == -3
 
 
 def test_coding_gain_argument_errors_host_only():
