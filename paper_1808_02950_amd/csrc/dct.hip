@@ -380,8 +380,13 @@ __device__ __forceinline__ void make_kops(const DctArgs &a, int lane, KOps &K) {
 }
 
 // the lane's two block rows 2g, 2g+1 (8 bytes each)
+// (the plane's fields are read again where they are used: an empty asm makes
+// the index opaque, so the compiler does not keep the fields of the eight
+// tiles in flight in scalar registers, which it would spill to vector lanes)
 __device__ __forceinline__ void load_rows(const DctArgs &a, const DTile &T, int g, u32x2 (&px)[2]) {
-    const PlaneArg &P = a.pl[T.p];
+    int pi = T.p;
+    asm volatile("" : "+s"(pi));
+    const PlaneArg &P = a.pl[pi];
     const uint8_t *base = a.in + int64_t(T.f) * a.fs_in + P.in_off;
     const uint32_t off = T.in_off + __umul24(uint32_t(2 * g), uint32_t(P.pitch_in));
     px[0] = __builtin_nontemporal_load((const u32x2 *)(base + off));
@@ -393,7 +398,9 @@ __device__ __forceinline__ void load_rows(const DctArgs &a, const DTile &T, int 
 template <int MODE>
 __device__ __forceinline__ uint32_t process_rows(const DctArgs &a, const DTile &T, const u32x2 (&px)[2],
                                                  const KOps &K, int g) {
-    const PlaneArg &P = a.pl[T.p];
+    int pi = T.p;
+    asm volatile("" : "+s"(pi));
+    const PlaneArg &P = a.pl[pi];
     const int64_t cb = (int64_t(T.f) * a.blocks_per_frame + P.block_off + T.b) * a.r + 4 * g;
     const float step = float(a.step);
     float bv[4];                                            // dequantised coefficients 4g..4g+3
