@@ -346,6 +346,54 @@ struct Prepared {
     QuantTables qt;    // built-in kernels' quantiser constants
 };
 
+// The exact bounds depend only on the matrix (and the prefix length) and the
+// inverse one costs tens of microseconds of 128-bit arithmetic, more than a
+// small image's kernel: each thread keeps the last few results, keyed by the
+// matrix bytes and r, since a caller usually repeats one transform.
+struct BoundEntry {
+    bool valid = false;
+    int8_t T[64];
+    int32_t n[8];
+    int r;                 // -1: only the forward bound is filled
+    int64_t fwd, inv;
+};
+constexpr int kBoundSlots = 8;
+static thread_local BoundEntry g_bounds[kBoundSlots];
+static thread_local int g_bound_next = 0;
+
+static BoundEntry *bound_lookup(const adct_matrix &m, int r) {
+    for (BoundEntry &e : g_bounds)
+        if (e.valid && (e.r == r || r < 0) && memcmp(e.T, m.T, sizeof(e.T)) == 0 && memcmp(e.n, m.n, sizeof(e.n)) == 0)
+            return &e;
+    return nullptr;
+}
+
+static int64_t fwd_bound_cached(const adct_matrix &m) {
+    if (const BoundEntry *e = bound_lookup(m, -1)) return e->fwd;
+    BoundEntry &e = g_bounds[g_bound_next];
+    g_bound_next = (g_bound_next + 1) % kBoundSlots;
+    e.valid = true;
+    memcpy(e.T, m.T, sizeof(e.T));
+    memcpy(e.n, m.n, sizeof(e.n));
+    e.r = -1;
+    e.fwd = fwd_bound(m);
+    e.inv = 0;
+    return e.fwd;
+}
+
+static int64_t inv_bound_cached(const adct_matrix &m, int r) {
+    if (const BoundEntry *e = bound_lookup(m, r); e && e->r == r) return e->inv;
+    BoundEntry &e = g_bounds[g_bound_next];
+    g_bound_next = (g_bound_next + 1) % kBoundSlots;
+    e.valid = true;
+    memcpy(e.T, m.T, sizeof(e.T));
+    memcpy(e.n, m.n, sizeof(e.n));
+    e.r = r;
+    e.fwd = fwd_bound(m);
+    e.inv = inv_bound(m, r);
+    return e.inv;
+}
+
 adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int quant_step,
                     bool need_int16_coef, Prepared *out, CodecArgs *a) {
     if (t == ADCT_DCT) return fail(ADCT_ENOTSUP, "the exact DCT runs through the MFMA comparator path");
@@ -383,14 +431,14 @@ adct_status prepare(adct_transform_id t, const adct_matrix *custom, int r, int q
             }
         if (out->settle) out->runtime = true;
     }
-    const int64_t fb = fwd_bound(out->m);
+    const int64_t fb = fwd_bound_cached(out->m);
     if (!out->quant) {
         if (need_int16_coef && fb > 32767)
             return fail(ADCT_EOVERFLOW, "the integer stage of this transform exceeds int16; request coef_scaled");
         if (out->runtime) {
             if (!rt_words_fit(out->m, std::max<int64_t>(fb, 32767)))
                 return fail(ADCT_EOVERFLOW, "exact inverse of this matrix exceeds 64-bit words");
-        } else if (2 * inv_bound(out->m, r) + (int64_t(1) << 22) >= (int64_t(1) << 31)) {
+        } else if (2 * inv_bound_cached(out->m, r) + (int64_t(1) << 22) >= (int64_t(1) << 31)) {
             return fail(ADCT_EOVERFLOW, "inverse numerator exceeds int32");
         }
     } else if (out->runtime && fb >= kRtMaxQuantY) {
@@ -673,8 +721,8 @@ adct_status adct_transform_bounds(adct_transform_id id, const adct_matrix *custo
     if (quant_step < 0) return fail(ADCT_ERANGE, "quant_step < 0");
     for (int k = 0; k < 8; ++k)
         if (m.n[k] <= 0) return fail(ADCT_EINVAL, "matrix has a zero row");
-    if (fwd) *fwd = fwd_bound(m);
-    if (inv) *inv = inv_bound(m, r);
+    if (fwd) *fwd = fwd_bound_cached(m);
+    if (inv) *inv = inv_bound_cached(m, r);
     return ADCT_OK;
 }
 

@@ -71,6 +71,26 @@ def test_inverse_bound_is_attained(name, r):
     assert best == bound
 
 
+def test_bounds_are_memoised_consistently():
+    """The library keeps the last few exact bounds per thread, keyed by the
+    matrix bytes and r: more distinct (matrix, r) pairs than it keeps, asked in
+    an interleaved order (so entries are evicted and refilled), always give
+    the values of the first asking; a caller matrix equal to a built-in one
+    shares its entries, and a matrix differing in one entry does not."""
+    keys = [(name, r) for name in ("T1", "T2", "LO", "T6", "RDCT", "T4") for r in (3, 10)]
+    first = {k: A.transform_bounds(*k) for k in keys}
+    for rep in range(3):
+        for k in (keys[rep::3] + keys[::-1]):
+            assert A.transform_bounds(*k) == first[k], k
+    t1 = np.array(M.T1, dtype=np.int64)
+    assert A.transform_bounds("CUSTOM", 10, custom=t1) == first[("T1", 10)]
+    t1b = t1.copy()
+    t1b[0] *= 2                               # another matrix (row 0 doubled): other bounds
+    fb, ib = A.transform_bounds("CUSTOM", 10, custom=t1b)
+    assert (fb, ib) != first[("T1", 10)] and fb == 4 * 255 * 64   # Y[0][0] of a block of 255s
+    assert A.transform_bounds("T1", 10) == first[("T1", 10)]
+
+
 def _call(fn, *args):
     return getattr(A.lib(), fn)(*args)
 
