@@ -435,6 +435,36 @@ int adjugate_det(const int8_t *T, int64_t adj[64], int64_t *det) {
     return 0;
 }
 
+// The adjugate takes 64 fraction-free 7 x 7 eliminations in 128-bit integers,
+// tens of microseconds of host time per call: each thread keeps the last few
+// results keyed by the matrix bytes (callers repeat one matrix over images).
+struct AdjEntry {
+    bool valid = false;
+    int8_t T[64];
+    int status;
+    int64_t adj[64], det;
+};
+constexpr int kAdjSlots = 4;
+thread_local AdjEntry g_adj[kAdjSlots];
+thread_local int g_adj_next = 0;
+
+int adjugate_det_cached(const int8_t *T, int64_t adj[64], int64_t *det) {
+    for (const AdjEntry &e : g_adj)
+        if (e.valid && memcmp(e.T, T, 64) == 0) {
+            memcpy(adj, e.adj, sizeof(e.adj));
+            *det = e.det;
+            return e.status;
+        }
+    AdjEntry &e = g_adj[g_adj_next];
+    g_adj_next = (g_adj_next + 1) % kAdjSlots;
+    e.status = adjugate_det(T, e.adj, &e.det);
+    memcpy(e.T, T, 64);
+    e.valid = true;
+    memcpy(adj, e.adj, sizeof(e.adj));
+    *det = e.det;
+    return e.status;
+}
+
 }  // namespace
 }  // namespace adct
 
@@ -454,7 +484,7 @@ extern "C" adct_status adct_evaluate_inverse(const uint8_t *frames, int64_t fram
     InvArgs a;
     memset(&a, 0, sizeof(a));
     int64_t adj[64], det = 0;
-    const int ad = adjugate_det(T, adj, &det);
+    const int ad = adjugate_det_cached(T, adj, &det);
     if (ad == 1) return fail(ADCT_EINVAL, "T is singular");
     if (ad == 2) return fail(ADCT_EOVERFLOW, "T is too large for exact float64 numerators");
     // T^-1 = adj / det: divide out the common factor of all entries and det
