@@ -162,6 +162,8 @@ struct JamArgs {
     double step_d;
     double skl[3][3];     // 1 / sqrt(n_k n_l) by (class of k, class of l)
     int32_t mu[3][3];     // sqrt(n_k n_l) where it is an integer, else 0
+    float qc1[3][3];      // where n_k n_l = mu^2, d = step mu: 1 / d, else 0
+    float qc2[3][3];      //   and (d + 1/2) / (2 d)
     int32_t cexact[3];    // L1 / n_k by class (exact inverse, no quantiser)
     double L;             // L1^2
     double inv_L;
@@ -274,7 +276,7 @@ __device__ __forceinline__ void load_row(const JamArgs &a, const JRow<N> &r, uin
 struct ColConst {
     double sk[3];     // s_k s_l / step by class of k (quantiser estimate)
     double dq[3];     // step s_k s_l (dequantisation)
-    int dd[3];        // step mu where n_k n_l = mu^2, else -1 (no exact ties)
+    float c1[3], c2[3];   // 1 / d, (d + 1/2) / (2 d) where n_k n_l = mu^2, d = step mu; c1 = 0 elsewhere
     int cex[3];       // L1 / n_k (exact inverse)
     int cexl;         // L1 / n_l
     uint32_t keep;    // bit k: coefficient (k, l) is inside the zig-zag prefix
@@ -318,17 +320,19 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
             const bool keep = (cc.keep >> k) & 1u;
             int q = Y[k];
             if constexpr (QUANT) {
-                // round-half-away(Y s_k s_l / step): the nearest integer m in float64
-                // is right unless the quotient is an exact half (possible only where
-                // n_k n_l = mu^2, dd = step mu; elsewhere dd = -1 and no test can
-                // hold); at a half m may have gone either way, and moves away from
-                // zero if it went towards it: m + 1/2 = Y / dd for Y > 0, m - 1/2 =
-                // Y / dd for Y < 0
-                int m = __double2loint(fma(double(q), cc.sk[ck], 6755399441055744.0));
-                const int t1 = __mul24(2 * m + 1, cc.dd[ck]);   // both below 2^23
-                const int t2 = t1 - 2 * cc.dd[ck];
-                m += (q > 0 && 2 * q == t1) ? 1 : 0;
-                m -= (q < 0 && 2 * q == t2) ? 1 : 0;
+                // round-half-away(Y s_k s_l / step).  Where n_k n_l = mu^2 the
+                // quotient is Y / d, d = step mu, and can be an exact half: there the
+                // magnitude floor((2|Y| + d + 1/2) / (2d)) is taken in float32, whose
+                // argument lies at least 1/(4d) from an integer while the rounded
+                // constants and the fma err by less than (2x + 1) 2^-24 with
+                // x < |Y| / d + 1, which is below 1/(4d) as 8|Y| + 12 d < 2^24 (checked
+                // on the host); the sign is copied on and the float truncated.
+                // Elsewhere the quotient is irrational, never a half, and the nearest
+                // integer of its float64 value is right.
+                const int mi = __double2loint(fma(double(q), cc.sk[ck], 6755399441055744.0));
+                const float yf = float(q);
+                const int mr = int(copysignf(fmaf(fabsf(yf), cc.c1[ck], cc.c2[ck]), yf));
+                const int m = cc.c1[ck] != 0.f ? mr : mi;
                 q = keep ? m : 0;
                 B[k] = double(q) * cc.dq[ck];
             } else {
@@ -433,10 +437,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N == 16 && B
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double skl = cl == 0 ? a.skl[c][0] : cl == 1 ? a.skl[c][1] : a.skl[c][2];
-            const int mu = cl == 0 ? a.mu[c][0] : cl == 1 ? a.mu[c][1] : a.mu[c][2];
             cc.sk[c] = skl * a.inv_step;
             cc.dq[c] = skl * a.step_d;
-            cc.dd[c] = mu ? mu * a.step : -1;
+            cc.c1[c] = cl == 0 ? a.qc1[c][0] : cl == 1 ? a.qc1[c][1] : a.qc1[c][2];
+            cc.c2[c] = cl == 0 ? a.qc2[c][0] : cl == 1 ? a.qc2[c][1] : a.qc2[c][2];
             cc.cex[c] = a.cexact[c];
         }
         cc.cexl = cl == 0 ? a.cexact[0] : cl == 1 ? a.cexact[1] : a.cexact[2];
@@ -624,7 +628,27 @@ extern "C" adct_status adct_jam_evaluate_stream(const uint8_t *frames, int64_t f
                 if (int64_t(s) * s == v) m = s;
             a.mu[i][k] = m;
             a.skl[i][k] = 1.0 / sqrt(double(v));
+            const double d = double(m) * quant_step;
+            a.qc1[i][k] = m && quant_step ? float(1.0 / d) : 0.f;
+            a.qc2[i][k] = m && quant_step ? float((d + 0.5) / (2.0 * d)) : 0.f;
         }
+    // the float32 quantiser of the classes with exact halves needs 8 |Y| + 12 d < 2^24
+    // (|Y| <= 255 (max row sum of |T|)^2, d = step mu)
+    if (quant_step) {
+        int8_t T[32 * 32];
+        jam_matrix_host(N, T);
+        int64_t rs = 0;
+        for (int k = 0; k < N; ++k) {
+            int64_t s = 0;
+            for (int m = 0; m < N; ++m) s += std::abs(int(T[k * N + m]));
+            rs = std::max(rs, s);
+        }
+        int64_t mu_max = 0;
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) mu_max = std::max<int64_t>(mu_max, a.mu[i][k]);
+        if (8 * 255 * rs * rs + 12 * mu_max * quant_step >= (int64_t(1) << 24))
+            return fail(ADCT_ERANGE, "quant_step too large for the exact quantiser");
+    }
     const int64_t L1 = int64_t(c) * 4 * 9 * 10 / 2;   // lcm(4c, 9c, 10c) = 180 c
     for (int i = 0; i < 3; ++i) a.cexact[i] = int32_t(L1 / (int64_t(c) * dv[i]));
     a.L = double(L1) * double(L1);

@@ -3,11 +3,12 @@
 
 Bar: reconstructions, squared errors and coefficients bit-exact.  Without a
 quantiser both sides reconstruct in exact rational arithmetic.  With one, the
-levels are exact (integer arithmetic where the quotient is rational; float64
-where it is irrational, which never sits within float64 error of a half for
-these magnitudes), and the float64 reconstruction can only differ from the
-oracle's exactly settled one within float64 error of a half, which the allowed
-steps (multiples of N) keep away from exact halves."""
+levels are exact (where the quotient is rational, a float32 form whose error is
+bounded below the distance to the nearest integer; float64 where it is
+irrational, which never sits within float64 error of a half for these
+magnitudes), and the float64 reconstruction can only differ from the oracle's
+exactly settled one within float64 error of a half, which the allowed steps
+(multiples of N) keep away from exact halves."""
 
 import numpy as np
 import pytest
@@ -169,3 +170,45 @@ def test_jam_degenerate_shapes_and_largest_step(cuda, n):
             want = jam.evaluate(img, TN[n], r, step)
             assert np.array_equal(coef, want["coef_int"]), (shape, r, step)
             assert np.array_equal(rec, want["rec"]) and sse == want["sse"], (shape, r, step)
+
+
+def _dc_blocks(n, sums, per_row=256):
+    """A plane of n x n blocks in raster order whose pixel sums are `sums`
+    (255s first, then the remainder, then zeros), padded with zero blocks."""
+    nb = len(sums)
+    rows = (nb + per_row - 1) // per_row
+    s = np.zeros(rows * per_row, dtype=np.int64)
+    s[:nb] = sums
+    p = np.arange(n * n, dtype=np.int32)[None, :]
+    full = (s // 255).astype(np.int32)[:, None]
+    rem = (s % 255).astype(np.int32)[:, None]
+    vals = np.where(p < full, 255, np.where(p == full, rem, 0)).astype(np.uint8)
+    img = vals.reshape(rows, per_row, n, n).transpose(0, 2, 1, 3).reshape(rows * n, per_row * n)
+    return np.ascontiguousarray(img)
+
+
+@pytest.mark.parametrize("n,lo,hi", [(16, 0, 255 * 256 + 1), (32, 0, 65536), (32, 255 * 1024 - 65535, 255 * 1024 + 1)])
+def test_jam_dc_levels_every_sum(cuda, n, lo, hi):
+    """The DC level for every pixel sum S in [lo, hi) (for N = 16 every sum a
+    block can have), at steps N, 3N and 7N: round-half-away(S / (n_0 step)) with
+    n_0 = N, so every sum that is an odd multiple of n_0 step / 2 is an exact
+    half.  The closed form, in integers, is checked against the oracle on a row
+    of exact halves and their neighbours."""
+    import torch
+    sums = np.arange(lo, hi, dtype=np.int64)
+    img = _dc_blocks(n, sums)
+    h, w = img.shape
+    frames = _dev(img.reshape(1, -1), cuda)
+    nb = A.jam_blocks_per_frame([(0, h, w, w)], n)
+    coef = torch.empty(nb, dtype=torch.int32, device=cuda)
+    for step in (n, 3 * n, 7 * n):
+        A.jam_evaluate_stream(frames, [(0, h, w, w)], n, 1, step, coef=coef)
+        got = coef.cpu().numpy()[:len(sums)].astype(np.int64)
+        d = n * step
+        want = (2 * sums + d) // (2 * d)
+        assert np.array_equal(got, want), (n, step, int(np.nonzero(got != want)[0][0]))
+        halves = d * (2 * np.arange(1, 9, dtype=np.int64) + 1) // 2
+        probe = np.concatenate([halves - 1, halves, halves + 1])
+        probe = probe[(probe >= 0) & (probe <= 255 * n * n)]
+        ref = jam.evaluate(_dc_blocks(n, probe, per_row=len(probe)), TN[n], 1, step)["coef_int"][:, 0]
+        assert np.array_equal(ref.astype(np.int64), (2 * probe + d) // (2 * d))
