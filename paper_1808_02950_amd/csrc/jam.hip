@@ -374,14 +374,23 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
         // sum (q - a)^2 = sum q^2 + sum a^2 - 2 sum q a
         const int ncol = min(N, Pl.W - rw.x0);
         unsigned sq = 0, cross = 0;
+        if (rw.full) {                     // the whole row lies inside the plane
 #pragma unroll
-        for (int v = 0; v < NW; ++v) {
-            const int nb = min(max(ncol - 4 * v, 0), 4);
-            const uint32_t msk = nb >= 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1u);
-            const uint32_t ov = o[v] & msk, pv = pix[v] & msk;
-            sq = __builtin_amdgcn_udot4(ov, ov, sq, false);
-            sq = __builtin_amdgcn_udot4(pv, pv, sq, false);
-            cross = __builtin_amdgcn_udot4(ov, pv, cross, false);
+            for (int v = 0; v < NW; ++v) {
+                sq = __builtin_amdgcn_udot4(o[v], o[v], sq, false);
+                sq = __builtin_amdgcn_udot4(pix[v], pix[v], sq, false);
+                cross = __builtin_amdgcn_udot4(o[v], pix[v], cross, false);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                const int nb = min(max(ncol - 4 * v, 0), 4);
+                const uint32_t msk = nb >= 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1u);
+                const uint32_t ov = o[v] & msk, pv = pix[v] & msk;
+                sq = __builtin_amdgcn_udot4(ov, ov, sq, false);
+                sq = __builtin_amdgcn_udot4(pv, pv, sq, false);
+                cross = __builtin_amdgcn_udot4(ov, pv, cross, false);
+            }
         }
         e = sq - 2u * cross;
         if (a.out) {
