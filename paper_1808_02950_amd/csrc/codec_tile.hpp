@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "adct_internal.hpp"
+#include "wave.hpp"
 
 namespace adct {
 namespace {
@@ -65,11 +66,7 @@ __device__ __forceinline__ int quant_irrational(int y, double skl, double inv_st
     return rne_i32(double(y) * skl * inv_step);
 }
 
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ unsigned wave_sum(unsigned v) { return wave_sum_u32(v); }
 
 // A wave's unit of work: 64 consecutive blocks of one plane of one frame.
 struct Tile {

@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include "adct_internal.hpp"
+#include "wave.hpp"
 
 namespace adct {
 namespace {
@@ -206,8 +207,7 @@ __device__ __forceinline__ void process_dtile(const DctArgs &a, const DTile &T, 
     }
     if constexpr (MODE == kEvaluate) {
         unsigned e = T.active ? sq - 2u * cross : 0u;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+        e = wave_sum_u32(e);
         if (lane == 0 && e) atomicAdd(a.sse + int64_t(T.f) * a.n_planes + T.p, (unsigned long long)e);
     }
 }
@@ -525,8 +525,7 @@ __device__ __forceinline__ void process_group(const DctArgs &a, const DGroup &G,
                               G.t[q + 1 < kGroup ? q + 1 : q].p != G.t[q].p;
             if (last && G.live[q]) {                        // wave-uniform
                 uint32_t s = e;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+                s = wave_sum_u32(s);
                 if (lane == 0 && s)
                     atomicAdd(a.sse + int64_t(G.t[q].f) * a.n_planes + G.t[q].p, (unsigned long long)s);
                 e = 0;

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "adct_internal.hpp"
+#include "wave.hpp"
 
 namespace adct {
 namespace {
@@ -185,20 +186,7 @@ __device__ __forceinline__ int rne_div_exact(double n, double L, double inv_L) {
     return qi + ((twice > L || (twice == L && (qi & 1))) ? 1 : 0);
 }
 
-// Sum over the 64 lanes on the DPP crossbar, without LDS: quad swaps, then
-// rotations by 4 and 8 lanes, leave every lane with its 16-lane row's sum;
-// the row broadcasts add row 0 into row 1 and row 2 into row 3, then lane 31
-// into rows 2 and 3 (disabled rows add the old value 0), so lane 63 holds the
-// total, which readlane returns.
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-    v += unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0xb1, 0xf, 0xf, false));    // quad_perm [1,0,3,2]
-    v += unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x4e, 0xf, 0xf, false));    // quad_perm [2,3,0,1]
-    v += unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x124, 0xf, 0xf, false));   // row_ror:4
-    v += unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x128, 0xf, 0xf, false));   // row_ror:8
-    v += unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xa, 0xf, false));   // row_bcast:15
-    v += unsigned(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xc, 0xf, false));   // row_bcast:31
-    return unsigned(__builtin_amdgcn_readlane(int(v), 63));
-}
+__device__ __forceinline__ unsigned wave_sum(unsigned v) { return wave_sum_u32(v); }
 
 struct JTile {
     int f, p, by, tx;     // frame, plane, block-row, tile inside the block-row

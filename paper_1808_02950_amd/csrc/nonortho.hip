@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "adct_internal.hpp"
+#include "wave.hpp"
 
 namespace adct {
 namespace {
@@ -53,11 +54,7 @@ struct InvArgs {
     InvPlane pl[kMaxPlanes];
 };
 
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ unsigned wave_sum(unsigned v) { return wave_sum_u32(v); }
 
 // round-half-to-even(n / den) clipped to [0, 255]; n and den integers held
 // exactly in doubles
