@@ -365,6 +365,25 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
         else px = rne_div_exact(A[m], a.L, a.inv_L);
         o[m >> 2] |= uint32_t(px) << (8 * (m & 3));
     }
+    // 32-point: the four lanes that hold image rows j and j + 16 of the tile
+    // (lanes j, j + 16 of the left block, j + 32, j + 48 of the right block,
+    // j < 16) trade 16-byte quarters, so that each store instruction writes 16
+    // whole 64-byte rows: after v_permlane16_swap (which exchanges the odd
+    // 16-lane rows of its first operand with the even rows of its second) a lane
+    // holds in sx the quarter 2 b + h of row j and in sy that of row j + 16
+    // (h = lane / 16 % 2).  Not in the wide-band kernels, which have no
+    // registers to spare.
+    uint32_t sx[4] = {0u, 0u, 0u, 0u}, sy[4] = {0u, 0u, 0u, 0u};
+    bool paired = false;                  // both blocks of the tile inside the plane (wave-uniform)
+    if constexpr (N == 32 && BAND < N - 1) {
+        paired = (rw.bx | 1) * N + N <= Pl.W;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const auto sw = __builtin_amdgcn_permlane16_swap(o[k], o[4 + k], false, false);
+            sx[k] = sw[0];
+            sy[k] = sw[1];
+        }
+    }
     unsigned e = 0;
     if (rw.active && rw.y < Pl.H) {
         // squared error from byte dot products, bytes past the plane masked off:
@@ -390,7 +409,7 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
             }
         }
         e = sq - 2u * cross;
-        if (a.out) {
+        if (a.out && !paired) {
             uint8_t *dst = a.out + int64_t(rw.f) * a.fs_out + Pl.out_off +
                            (__umul24(uint32_t(rw.y), uint32_t(Pl.pitch_out)) + uint32_t(rw.x0));
             if (rw.full) {
@@ -409,6 +428,16 @@ __device__ __forceinline__ void process_tile(const JamArgs &a, const JRow<N> &rw
                     if (m < ncol) dst[m] = uint8_t(o[m >> 2] >> (8 * (m & 3)));
             }
         }
+    }
+    if (paired && a.out) {
+        const int h = (lane >> 4) & 1;
+        const int y1 = rw.y - 16 * h;     // row j of the tile (j = lane % 16)
+        uint8_t *p1 = a.out + int64_t(rw.f) * a.fs_out + Pl.out_off +
+                      (__umul24(uint32_t(y1), uint32_t(Pl.pitch_out)) + uint32_t(rw.x0 + 16 * h));
+        if (y1 < Pl.H) __builtin_nontemporal_store(u32x4{sx[0], sx[1], sx[2], sx[3]}, (u32x4 *)p1);
+        if (y1 + 16 < Pl.H)
+            __builtin_nontemporal_store(u32x4{sy[0], sy[1], sy[2], sy[3]},
+                                        (u32x4 *)(p1 + 16 * uint32_t(Pl.pitch_out)));
     }
     // squared errors: one atomic per (frame, plane) run of the wave
     const int fp = rw.f * a.n_planes + rw.p;
