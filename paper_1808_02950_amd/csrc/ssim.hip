@@ -136,7 +136,10 @@ __device__ __forceinline__ void ssim_row(const SsimArgs &a, const uint8_t *rb, c
 // seams, then run on the same L2 at about the same time.
 __global__ __launch_bounds__(256) void k_ssim(const SsimArgs a) {
     __shared__ uint32_t rows[4][64 + kWin - 1];
-    const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
+    // the wave index read from the first lane, so that the tile, its plane and
+    // every row bound below are known to be wave-uniform and the per-row
+    // window tests run on the scalar unit instead of as lane masks
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = int(threadIdx.x & 63);
     const int gw = xcd_swizzle(int(blockIdx.x), int(gridDim.x)) * 4 + wave;
     if (gw >= a.n_frames * a.tiles_per_frame) return;          // whole wave leaves
     const int f = gw / a.tiles_per_frame;
