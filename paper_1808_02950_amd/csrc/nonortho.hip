@@ -79,7 +79,10 @@ __global__ __launch_bounds__(256) void k_inverse_codec(const InvArgs a) {
     const int total = a.n_frames * a.waves_per_frame;
     unsigned long long acc = 0;
     int acc_fp = -1;
-    for (int gw = int(blockIdx.x) * 4 + int(threadIdx.x >> 6); gw < total; gw += int(gridDim.x) * 4) {
+    // the wave index from the first lane: tile, frame and plane are then known
+    // to be wave-uniform and stay on the scalar unit
+    for (int gw = int(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)); gw < total;
+         gw += int(gridDim.x) * 4) {
         const int f = gw / a.waves_per_frame;
         const int w = gw - f * a.waves_per_frame;
         int p = 0;
