@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "adct_internal.hpp"
+#include "wave.hpp"
 
 namespace adct {
 namespace {
@@ -149,11 +150,8 @@ __device__ __forceinline__ uint32_t pix_energy(const uint32_t (&pix)[8][2]) {
     return e;
 }
 
-__device__ __forceinline__ unsigned wave_add(unsigned v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+// (every lane of the wave is active where it is called)
+__device__ __forceinline__ unsigned wave_add(unsigned v) { return wave_sum_u32(v); }
 
 __device__ __forceinline__ int pix_at(const uint32_t (&pix)[8][2], int x, int y) {
     return int((pix[x][y >> 2] >> (8 * (y & 3))) & 0xffu);
