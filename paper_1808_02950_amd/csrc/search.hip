@@ -92,6 +92,26 @@ __device__ __forceinline__ double cos_row(const int (&v)[8], double inv, const D
     return dot * inv;
 }
 
+// The same product with the rows read from LDS.  The scan kernels over the whole
+// space keep all 64 entries there: as a kernel argument they are 128 scalar
+// registers, more than a wave holds beside the rest, and the compiler reloads
+// the spilled ones lane by lane for every candidate.
+__device__ __forceinline__ double cos_row_lds(const int (&v)[8], double inv, const double *c, int r) {
+    double dot = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dot = fma(double(v[e]), c[8 * r + e], dot);
+    return dot * inv;
+}
+
+// the rows into a workgroup's LDS copy (every thread calls it, before any use)
+__device__ __forceinline__ void rows_to_lds(const DctRows &rows, double *sc) {
+    for (int i = int(threadIdx.x); i < 64; i += int(blockDim.x)) sc[i] = rows.c[i];
+}
+// at the top of each candidate: the rows are read from LDS where they are used
+// (a compiler-only barrier; without it the compiler would hoist all 64 into
+// 128 vector registers)
+__device__ __forceinline__ void rows_fence() { asm volatile("" ::: "memory"); }
+
 // monotone map of a double onto uint64 (for atomicMax)
 __device__ __forceinline__ unsigned long long order_key(double x) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(x);
@@ -272,10 +292,13 @@ __global__ __launch_bounds__(256) void k_hist(int64_t n, const uint2 *vec, const
                                              const double *invt, const DctRows rows, unsigned *hist,
                                              uint2 *codes) {
     __shared__ unsigned h[8 * kHistBins];
+    __shared__ double sc[64];
     for (int i = threadIdx.x; i < 8 * kHistBins; i += blockDim.x) h[i] = 0;
+    rows_to_lds(rows, sc);
     __syncthreads();
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
+        rows_fence();
         uint32_t c0 = 0, c1 = 0;
         if (!(primitive && !prim[i])) {
             const uint2 p = vec[i];
@@ -284,7 +307,7 @@ __global__ __launch_bounds__(256) void k_hist(int64_t n, const uint2 *vec, const
             const double inv = inv_norm(p, invt);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                const int bn = angle_bin(cos_row(v, inv, rows, r));
+                const int bn = angle_bin(cos_row_lds(v, inv, sc, r));
                 if (bn >= 0) atomicAdd(&h[r * kHistBins + bn], 1u);
                 const uint32_t code = uint32_t(min(max(bn + 1, 0), 255));
                 if (r < 4) c0 |= code << (8 * r); else c1 |= code << (8 * (r - 4));
@@ -308,8 +331,12 @@ __global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const uint2 *ve
                                                      Thresholds th,
                                                      int64_t *out_idx, double *out_cos,
                                                      unsigned long long *count) {
+    __shared__ double sc[64];
+    rows_to_lds(rows, sc);
+    __syncthreads();
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
+        rows_fence();
         if (primitive && !prim[i]) continue;
         const uint2 p = vec[i];
         int v[8];
@@ -317,7 +344,7 @@ __global__ __launch_bounds__(256) void k_topk_collect(int64_t n, const uint2 *ve
         const double inv = inv_norm(p, invt);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const double c = cos_row(v, inv, rows, r);
+            const double c = cos_row_lds(v, inv, sc, r);
             if (angle_bin(c) >= th.bin[r]) {
                 const unsigned long long pos = atomicAdd(count + r, 1ull);
                 if (int64_t(pos) < th.cap[r]) {
@@ -336,8 +363,12 @@ __global__ __launch_bounds__(256) void k_topk_collect_codes(int64_t n, const uin
                                                            const double *invt, const DctRows rows,
                                                            Thresholds th, int64_t *out_idx, double *out_cos,
                                                            unsigned long long *count) {
+    __shared__ double sc[64];
+    rows_to_lds(rows, sc);
+    __syncthreads();
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
+        rows_fence();
         const uint2 cw = codes[i];
         uint32_t hit = 0;
 #pragma unroll
@@ -355,7 +386,7 @@ __global__ __launch_bounds__(256) void k_topk_collect_codes(int64_t n, const uin
             const unsigned long long pos = atomicAdd(count + r, 1ull);
             if (int64_t(pos) < th.cap[r]) {
                 out_idx[th.off[r] + int64_t(pos)] = i;
-                out_cos[th.off[r] + int64_t(pos)] = cos_row(v, inv, rows, r);
+                out_cos[th.off[r] + int64_t(pos)] = cos_row_lds(v, inv, sc, r);
             }
         }
     }
